@@ -13,6 +13,7 @@ Functions follow the paper's definitions:
   (Def 2.3, exact).
 * ``scan(g, p, q, mu)`` - labels (minimum core id of the cluster, -1 when
   unclassified) and roles (0 unclassified, 1 core, 2 border); Defs 2.4-2.6.
+* ``cluster(g, counts, p, q, mu)`` - the same from counts already computed.
 """
 from __future__ import annotations
 
@@ -61,6 +62,8 @@ class Oracle:
         lib.oracle_counts_all.restype = ctypes.c_int
         lib.oracle_scan.argtypes = [i32, vp, vp, i64, i64, i32, ctypes.c_int, vp, vp, vp]
         lib.oracle_scan.restype = ctypes.c_int
+        lib.oracle_cluster.argtypes = [i32, vp, vp, vp, i64, i64, i32, vp, vp]
+        lib.oracle_cluster.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         self.lib = lib
 
@@ -105,6 +108,20 @@ class Oracle:
             return labels, roles, cnt[: int(rp[-1])]
         return labels, roles
 
+    def cluster(self, g, counts: np.ndarray, p: int, q: int, mu: int):
+        """Clustering from per-arc closed counts previously returned by counts()."""
+        n, rp, ci = self._arrays(g)
+        cnt = np.ascontiguousarray(counts, dtype=np.int32)
+        if cnt.size == 0:
+            cnt = np.zeros(1, dtype=np.int32)
+        labels = np.empty(max(1, n), dtype=np.int32)
+        roles = np.empty(max(1, n), dtype=np.uint8)
+        rc = self.lib.oracle_cluster(n, _vp(rp), _vp(ci), _vp(cnt), int(p), int(q), int(mu),
+                                     _vp(labels), _vp(roles))
+        if rc != 0:
+            raise ValueError(f"oracle_cluster failed with code {rc}")
+        return labels[:n], roles[:n]
+
     def max_threads(self) -> int:
         return int(self.lib.oracle_max_threads())
 
@@ -137,6 +154,10 @@ def counts(g, threads: int = 1) -> np.ndarray:
 
 def scan(g, p, q, mu, threads: int = 1, want_counts: bool = False):
     return default().scan(g, p, q, mu, threads, want_counts)
+
+
+def cluster(g, counts, p, q, mu):
+    return default().cluster(g, counts, p, q, mu)
 
 
 def max_threads() -> int:

@@ -172,8 +172,69 @@ int oracle_counts_all(int32_t n, const int64_t* rp, const int32_t* ci, int32_t* 
   return err ? OR_NOMEM : OR_OK;
 }
 
-/* Full clustering.  labels[n], roles[n] are outputs; counts (nnz) is an
- * optional output of the per-arc closed counts (NULL to skip). */
+/* Clustering from given per-arc closed counts (as produced by
+ * oracle_counts_all): Defs 2.3-2.6 and the border rule.  labels[n] and
+ * roles[n] are outputs. */
+int oracle_cluster(int32_t n, const int64_t* rp, const int32_t* ci, const int32_t* cnt, int64_t p,
+                   int64_t q, int32_t mu, int32_t* labels, uint8_t* roles) {
+  if (n < 0 || p < 1 || q < p || q > 0x7fffffffLL || mu < 2 || !labels || !roles)
+    return OR_INVAL;
+  const int64_t nnz = rp[n];
+  uint8_t* sim = (uint8_t*)malloc((size_t)(nnz > 0 ? nnz : 1));
+  uint8_t* core = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!sim || !core || !queue) {
+    free(sim); free(core); free(queue);
+    return OR_NOMEM;
+  }
+  /* Def 2.3: similarity of every arc. */
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t i = rp[u]; i < rp[u + 1]; ++i) {
+      const int32_t v = ci[i];
+      sim[i] = (uint8_t)oracle_similar(cnt[i], rp[u + 1] - rp[u] + 1, rp[v + 1] - rp[v] + 1, p, q);
+    }
+  /* Def 2.4: |N_eps[u]| = 1 (u itself) + number of similar neighbours. */
+  for (int32_t u = 0; u < n; ++u) {
+    int64_t ne = 1;
+    for (int64_t i = rp[u]; i < rp[u + 1]; ++i) ne += sim[i];
+    core[u] = (uint8_t)(ne >= mu);
+  }
+  /* Defs 2.5-2.6: breadth-first search over similar core-core edges,
+   * seeds in ascending order, so each cluster's label is its smallest core. */
+  for (int32_t u = 0; u < n; ++u) labels[u] = -1;
+  for (int32_t s = 0; s < n; ++s) {
+    if (!core[s] || labels[s] != -1) continue;
+    int64_t head = 0, tail = 0;
+    labels[s] = s;
+    queue[tail++] = s;
+    while (head < tail) {
+      const int32_t x = queue[head++];
+      for (int64_t i = rp[x]; i < rp[x + 1]; ++i) {
+        const int32_t v = ci[i];
+        if (sim[i] && core[v] && labels[v] == -1) {
+          labels[v] = s;
+          queue[tail++] = v;
+        }
+      }
+    }
+  }
+  /* Borders: the minimum label among similar core neighbours. */
+  for (int32_t v = 0; v < n; ++v) {
+    if (core[v]) { roles[v] = ROLE_CORE; continue; }
+    int32_t best = -1;
+    for (int64_t i = rp[v]; i < rp[v + 1]; ++i) {
+      const int32_t u = ci[i];
+      if (core[u] && sim[i] && (best < 0 || labels[u] < best)) best = labels[u];
+    }
+    roles[v] = best >= 0 ? ROLE_BORDER : ROLE_UNCLASSIFIED;
+    labels[v] = best;
+  }
+  free(sim); free(core); free(queue);
+  return OR_OK;
+}
+
+/* Full clustering: closed counts of every arc, then oracle_cluster.
+ * counts (nnz) is an optional output of the per-arc counts (NULL to skip). */
 int oracle_scan(int32_t n, const int64_t* rp, const int32_t* ci, int64_t p, int64_t q,
                 int32_t mu, int threads, int32_t* labels, uint8_t* roles, int32_t* counts) {
   if (n < 0 || p < 1 || q < p || q > 0x7fffffffLL || mu < 2 || !labels || !roles)
@@ -184,61 +245,9 @@ int oracle_scan(int32_t n, const int64_t* rp, const int32_t* ci, int64_t p, int6
     cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     if (!cnt) return OR_NOMEM;
   }
-  uint8_t* sim = (uint8_t*)malloc((size_t)(nnz > 0 ? nnz : 1));
-  uint8_t* core = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
-  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-  if (!sim || !core || !queue) {
-    if (!counts) free(cnt);
-    free(sim); free(core); free(queue);
-    return OR_NOMEM;
-  }
   int rc = oracle_counts_all(n, rp, ci, cnt, threads);
-  if (rc == OR_OK) {
-    /* Def 2.3: similarity of every arc. */
-    for (int32_t u = 0; u < n; ++u)
-      for (int64_t i = rp[u]; i < rp[u + 1]; ++i) {
-        const int32_t v = ci[i];
-        sim[i] = (uint8_t)oracle_similar(cnt[i], rp[u + 1] - rp[u] + 1, rp[v + 1] - rp[v] + 1, p, q);
-      }
-    /* Def 2.4: |N_eps[u]| = 1 (u itself) + number of similar neighbours. */
-    for (int32_t u = 0; u < n; ++u) {
-      int64_t ne = 1;
-      for (int64_t i = rp[u]; i < rp[u + 1]; ++i) ne += sim[i];
-      core[u] = (uint8_t)(ne >= mu);
-    }
-    /* Defs 2.5-2.6: breadth-first search over similar core-core edges,
-     * seeds in ascending order, so each cluster's label is its smallest core. */
-    for (int32_t u = 0; u < n; ++u) labels[u] = -1;
-    for (int32_t s = 0; s < n; ++s) {
-      if (!core[s] || labels[s] != -1) continue;
-      int64_t head = 0, tail = 0;
-      labels[s] = s;
-      queue[tail++] = s;
-      while (head < tail) {
-        const int32_t x = queue[head++];
-        for (int64_t i = rp[x]; i < rp[x + 1]; ++i) {
-          const int32_t v = ci[i];
-          if (sim[i] && core[v] && labels[v] == -1) {
-            labels[v] = s;
-            queue[tail++] = v;
-          }
-        }
-      }
-    }
-    /* Borders: the minimum label among similar core neighbours. */
-    for (int32_t v = 0; v < n; ++v) {
-      if (core[v]) { roles[v] = ROLE_CORE; continue; }
-      int32_t best = -1;
-      for (int64_t i = rp[v]; i < rp[v + 1]; ++i) {
-        const int32_t u = ci[i];
-        if (core[u] && sim[i] && (best < 0 || labels[u] < best)) best = labels[u];
-      }
-      roles[v] = best >= 0 ? ROLE_BORDER : ROLE_UNCLASSIFIED;
-      labels[v] = best;
-    }
-  }
+  if (rc == OR_OK) rc = oracle_cluster(n, rp, ci, cnt, p, q, mu, labels, roles);
   if (!counts) free(cnt);
-  free(sim); free(core); free(queue);
   return rc;
 }
 

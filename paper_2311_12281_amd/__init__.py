@@ -1,0 +1,280 @@
+"""Python binding of the MI355X structural-clustering library.
+
+Argument marshalling only: every function below forwards to the C-ABI of the
+same name in ``libscan_mi355x.so`` (declared in ``include/scan.h``), and all
+computation happens in the library's HIP kernels.  There is no CPU fallback:
+if the library is not built, importing works but every call raises
+``LibraryNotBuilt``.
+
+Host arrays are numpy arrays; device buffers are raw addresses (int) obtained
+from ``scan_device_alloc``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscan_mi355x.so")
+
+SCAN_OK, SCAN_E_INVAL, SCAN_E_GRAPH, SCAN_E_RANGE, SCAN_E_NOMEM, SCAN_E_DEVICE = 0, -1, -2, -3, -4, -5
+SCAN_UNCLASSIFIED, SCAN_CORE, SCAN_BORDER = 0, 1, 2
+PHASES = ["init", "cores", "finalize", "hook", "merge", "flatten", "attach", "output"]
+NUM_PHASES = len(PHASES)
+NUM_BUCKETS = 6
+EXPORTED = [
+    "scan_opts_default", "scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
+    "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_eps_threshold",
+    "scan_last_stats", "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h",
+    "scan_memcpy_h2d", "scan_last_error", "scan_version",
+]
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class ScanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class scan_opts(ctypes.Structure):
+    _fields_ = [
+        ("device_budget_bytes", ctypes.c_uint64),
+        ("validate", ctypes.c_int32),
+        ("pruning", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class scan_stats(ctypes.Structure):
+    _fields_ = [
+        ("ms_total", ctypes.c_double),
+        ("ms_phase", ctypes.c_double * NUM_PHASES),
+        ("ms_cores_bucket", ctypes.c_double * NUM_BUCKETS),
+        ("edges", ctypes.c_int64),
+        ("bucket_edges", ctypes.c_int64 * NUM_BUCKETS),
+        ("evaluated", ctypes.c_int64 * NUM_PHASES),
+        ("bounded", ctypes.c_int64 * NUM_PHASES),
+        ("probes", ctypes.c_int64 * NUM_PHASES),
+        ("cores_bucket_evaluated", ctypes.c_int64 * NUM_BUCKETS),
+        ("cores_bucket_probes", ctypes.c_int64 * NUM_BUCKETS),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises LibraryNotBuilt if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryNotBuilt(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+        P = ctypes.POINTER
+        L.scan_opts_default.argtypes = [P(scan_opts)]
+        L.scan_opts_default.restype = None
+        L.scan_graph_create.argtypes = [i32, i64, vp, vp, P(scan_opts), P(vp)]
+        L.scan_graph_destroy.argtypes = [vp]
+        L.scan_graph_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
+        L.scan_run.argtypes = [vp, i64, i64, i32, vp, vp]
+        L.scan_run_device.argtypes = [vp, i64, i64, i32, vp, vp, vp]
+        L.scan_similarity.argtypes = [vp, vp]
+        L.scan_similarity_device.argtypes = [vp, vp, vp]
+        L.scan_eps_threshold.argtypes = [i64, i64, i64, i64]
+        L.scan_eps_threshold.restype = i64
+        L.scan_last_stats.argtypes = [vp, P(scan_stats)]
+        L.scan_device_alloc.argtypes = [u64, P(vp)]
+        L.scan_device_free.argtypes = [vp]
+        L.scan_memcpy_d2h.argtypes = [vp, vp, u64]
+        L.scan_memcpy_h2d.argtypes = [vp, vp, u64]
+        L.scan_last_error.restype = ctypes.c_char_p
+        L.scan_version.restype = ctypes.c_char_p
+        for name in ("scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
+                     "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_last_stats",
+                     "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h", "scan_memcpy_h2d"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SCAN_OK:
+        raise ScanError(rc, lib().scan_last_error().decode(errors="replace"))
+
+
+def _vp(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def scan_version() -> str:
+    return lib().scan_version().decode()
+
+
+def scan_last_error() -> str:
+    return lib().scan_last_error().decode(errors="replace")
+
+
+def scan_opts_default() -> scan_opts:
+    o = scan_opts()
+    lib().scan_opts_default(ctypes.byref(o))
+    return o
+
+
+def make_opts(budget: int = 0, validate: bool = True, pruning: bool = True, timing: bool = False,
+              stream: int | None = None) -> scan_opts:
+    o = scan_opts_default()
+    o.device_budget_bytes = int(budget)
+    o.validate = int(bool(validate))
+    o.pruning = int(bool(pruning))
+    o.timing = int(bool(timing))
+    o.hip_stream = stream
+    return o
+
+
+def scan_graph_create(n: int, nnz: int, row_ptr: np.ndarray, col_idx: np.ndarray,
+                      opts: scan_opts | None = None) -> ctypes.c_void_p:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if rp.shape[0] != n + 1:
+        raise ValueError("row_ptr must have n+1 entries")
+    if ci.shape[0] < nnz:
+        raise ValueError("col_idx shorter than nnz")
+    h = ctypes.c_void_p()
+    _check(lib().scan_graph_create(int(n), int(nnz), _vp(rp), _vp(ci) if nnz else None,
+                                   ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+    return h
+
+
+def scan_graph_destroy(g) -> None:
+    _check(lib().scan_graph_destroy(g))
+
+
+def scan_graph_info(g) -> tuple[int, int, int, int]:
+    n, nnz, m, dm = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().scan_graph_info(g, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(m), ctypes.byref(dm)))
+    return n.value, nnz.value, m.value, dm.value
+
+
+def scan_run(g, eps_num: int, eps_den: int, mu: int, labels: np.ndarray | None = None,
+             roles: np.ndarray | None = None):
+    n = scan_graph_info(g)[0]
+    labels = np.empty(max(n, 1), dtype=np.int32) if labels is None else labels
+    roles = np.empty(max(n, 1), dtype=np.uint8) if roles is None else roles
+    assert labels.dtype == np.int32 and roles.dtype == np.uint8 and labels.size >= n and roles.size >= n
+    _check(lib().scan_run(g, int(eps_num), int(eps_den), int(mu), _vp(labels), _vp(roles)))
+    return labels[:n], roles[:n]
+
+
+def scan_run_device(g, eps_num: int, eps_den: int, mu: int, d_labels: int, d_roles: int,
+                    stream: int | None = None) -> None:
+    _check(lib().scan_run_device(g, int(eps_num), int(eps_den), int(mu), ctypes.c_void_p(d_labels),
+                                 ctypes.c_void_p(d_roles), ctypes.c_void_p(stream) if stream else None))
+
+
+def scan_similarity(g, counts: np.ndarray | None = None) -> np.ndarray:
+    nnz = scan_graph_info(g)[1]
+    counts = np.empty(max(nnz, 1), dtype=np.int32) if counts is None else counts
+    _check(lib().scan_similarity(g, _vp(counts)))
+    return counts[:nnz]
+
+
+def scan_similarity_device(g, d_counts: int, stream: int | None = None) -> None:
+    _check(lib().scan_similarity_device(g, ctypes.c_void_p(d_counts),
+                                        ctypes.c_void_p(stream) if stream else None))
+
+
+def scan_eps_threshold(p: int, q: int, a: int, b: int) -> int:
+    return int(lib().scan_eps_threshold(int(p), int(q), int(a), int(b)))
+
+
+def scan_last_stats(g) -> dict:
+    s = scan_stats()
+    _check(lib().scan_last_stats(g, ctypes.byref(s)))
+    return {
+        "ms_total": s.ms_total,
+        "ms_phase": dict(zip(PHASES, list(s.ms_phase))),
+        "ms_cores_bucket": list(s.ms_cores_bucket),
+        "edges": s.edges,
+        "bucket_edges": list(s.bucket_edges),
+        "evaluated": dict(zip(PHASES, list(s.evaluated))),
+        "bounded": dict(zip(PHASES, list(s.bounded))),
+        "probes": dict(zip(PHASES, list(s.probes))),
+        "cores_bucket_evaluated": list(s.cores_bucket_evaluated),
+        "cores_bucket_probes": list(s.cores_bucket_probes),
+    }
+
+
+def scan_device_alloc(nbytes: int) -> int:
+    p = ctypes.c_void_p()
+    _check(lib().scan_device_alloc(int(nbytes), ctypes.byref(p)))
+    return int(p.value)
+
+
+def scan_device_free(ptr: int) -> None:
+    _check(lib().scan_device_free(ctypes.c_void_p(ptr)))
+
+
+def scan_memcpy_d2h(dst: np.ndarray, src: int, nbytes: int) -> None:
+    assert dst.nbytes >= nbytes
+    _check(lib().scan_memcpy_d2h(_vp(dst), ctypes.c_void_p(src), int(nbytes)))
+
+
+def scan_memcpy_h2d(dst: int, src: np.ndarray, nbytes: int) -> None:
+    assert src.nbytes >= nbytes
+    _check(lib().scan_memcpy_h2d(ctypes.c_void_p(dst), _vp(np.ascontiguousarray(src)), int(nbytes)))
+
+
+class Graph:
+    """Owning wrapper around a scan_graph handle."""
+
+    def __init__(self, n, row_ptr, col_idx, **opts):
+        self.opts = make_opts(**opts)
+        self.n = int(n)
+        self.nnz = int(row_ptr[-1]) if n > 0 else 0
+        self.handle = scan_graph_create(self.n, self.nnz, row_ptr, col_idx, self.opts)
+
+    @classmethod
+    def from_csr(cls, g, **opts):
+        return cls(g.n, g.row_ptr, g.col_idx, **opts)
+
+    def info(self):
+        return scan_graph_info(self.handle)
+
+    def run(self, p, q, mu):
+        return scan_run(self.handle, p, q, mu)
+
+    def run_device(self, p, q, mu, d_labels, d_roles, stream=None):
+        scan_run_device(self.handle, p, q, mu, d_labels, d_roles, stream)
+
+    def similarity(self):
+        return scan_similarity(self.handle)
+
+    def stats(self):
+        return scan_last_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            scan_graph_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

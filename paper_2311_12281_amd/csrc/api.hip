@@ -1,0 +1,443 @@
+// C-ABI of the library (declared in include/scan.h): graph creation, the
+// in-memory clustering run (GPUSCAN++ Algorithm 1 with Algorithms 2-3), the
+// exact per-arc closed counts, statistics and small device-memory helpers.
+#include "scan_internal.h"
+#include "../../include/scan.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+using namespace scan;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(SCAN_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(SCAN_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                   \
+  do {                                        \
+    hipError_t _e = (call);                   \
+    if (_e != hipSuccess) return fail_hip(_e, what); \
+  } while (0)
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+}  // namespace
+
+struct scan_graph {
+  int32_t n = 0;
+  int64_t nnz = 0, m = 0;
+  int32_t max_degree = 0;
+  int64_t bucket_off[kNumBuckets + 1] = {0};
+  scan_opts opts{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  // graph (read-only after create)
+  int64_t* d_rp = nullptr;
+  int32_t* d_ci = nullptr;
+  int2* d_edges = nullptr;
+  // per-run state
+  int32_t* d_lower = nullptr;
+  int32_t* d_upper = nullptr;
+  uint8_t* d_role = nullptr;
+  int32_t* d_parent = nullptr;
+  int32_t* d_label = nullptr;
+  uint8_t* d_state = nullptr;
+  unsigned long long* d_stats = nullptr;
+  int32_t* d_out_labels = nullptr;  // staging for the host-output entry points
+  uint8_t* d_out_roles = nullptr;
+  int32_t* d_counts = nullptr;      // staging for scan_similarity
+  hipEvent_t ev[SCAN_NUM_PHASES + kNumBuckets + 2] = {};
+  std::mutex lock;
+  scan_stats last{};
+};
+
+namespace {
+
+void release(scan_graph* g) {
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_edges, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+                  g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  for (auto& e : g->ev)
+    if (e) hipEventDestroy(e);
+  if (g->own_stream && g->stream) hipStreamDestroy(g->stream);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t count) {
+  return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+uint64_t footprint_bytes(int32_t n, int64_t nnz) {
+  const uint64_t m = (uint64_t)nnz / 2;
+  return 8ull * (n + 1) + 4ull * nnz + 8ull * m + 1ull * m + 22ull * n + 8ull * 64;
+}
+
+// Runs Algorithm 1 (with Algorithms 2 and 3) on g; outputs into device buffers.
+int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
+                   uint8_t* d_roles, hipStream_t s) {
+  if (p < 1 || q < p) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den (got %lld/%lld)",
+                                  (long long)p, (long long)q);
+  if (mu < 2) return fail(SCAN_E_INVAL, "mu must be >= 2 (got %d)", mu);
+  const int64_t gd = gcd64(p, q);
+  p /= gd;
+  q /= gd;
+  if ((unsigned __int128)q * (unsigned __int128)((uint64_t)g->max_degree + 1) >= ((unsigned __int128)1 << 32))
+    return fail(SCAN_E_RANGE, "eps denominator %lld with max degree %d exceeds the 64-bit test range",
+                (long long)q, g->max_degree);
+  const bool timing = g->opts.timing != 0;
+  const int n = g->n;
+  const int64_t m = g->m;
+  HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
+  auto mark = [&](int k) {
+    if (timing) hipEventRecord(g->ev[k], s);
+  };
+  EdgeArgs A{};
+  A.rp = g->d_rp;
+  A.ci = g->d_ci;
+  A.edges = g->d_edges;
+  A.state = g->d_state;
+  A.lower = g->d_lower;
+  A.upper = g->d_upper;
+  A.role = g->d_role;
+  A.parent = g->d_parent;
+  A.label = g->d_label;
+  A.counts = nullptr;
+  A.stats = g->d_stats;
+  A.p = (uint64_t)p;
+  A.q = (uint64_t)q;
+  A.mu = mu;
+  A.pruning = g->opts.pruning;
+  // Events: 0 start, then the end of each phase; the cores phase also marks
+  // the end of each bucket (slots SCAN_NUM_PHASES + 1 + k).
+  mark(0);
+  launch_init(s, n, g->d_rp, mu, g->d_lower, g->d_upper, g->d_role, g->d_parent);
+  launch_fill_u8(s, g->d_state, m, SIM_UNK);
+  mark(1);
+  for (int k = 0; k < kNumBuckets; ++k) {
+    A.e_begin = g->bucket_off[k];
+    A.e_end = g->bucket_off[k + 1];
+    A.bucket = k;
+    launch_edges(s, MODE_CORES, k, A);
+    mark(SCAN_NUM_PHASES + 1 + k);
+  }
+  mark(2);
+  launch_finalize_roles(s, n, mu, g->d_lower, g->d_role);
+  mark(3);
+  launch_hook(s, m, g->d_edges, g->d_state, g->d_role, g->d_parent);
+  mark(4);
+  for (int k = 0; k < kNumBuckets; ++k) {
+    A.e_begin = g->bucket_off[k];
+    A.e_end = g->bucket_off[k + 1];
+    A.bucket = k;
+    launch_edges(s, MODE_MERGE, k, A);
+  }
+  mark(5);
+  launch_flatten(s, n, g->d_role, g->d_parent, g->d_label);
+  mark(6);
+  for (int k = 0; k < kNumBuckets; ++k) {
+    A.e_begin = g->bucket_off[k];
+    A.e_end = g->bucket_off[k + 1];
+    A.bucket = k;
+    launch_edges(s, MODE_ATTACH, k, A);
+  }
+  mark(7);
+  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles);
+  mark(8);
+  HIP_TRY(hipGetLastError(), "kernel launch");
+  unsigned long long st[ST_COUNT];
+  HIP_TRY(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  scan_stats& L = g->last;
+  memset(&L, 0, sizeof(L));
+  L.edges = m;
+  for (int k = 0; k < kNumBuckets; ++k) {
+    L.bucket_edges[k] = g->bucket_off[k + 1] - g->bucket_off[k];
+    L.cores_bucket_evaluated[k] = (int64_t)st[ST_BUCKET_EVAL + k];
+    L.cores_bucket_probes[k] = (int64_t)st[ST_BUCKET_PROBES + k];
+  }
+  const int phase_of_mode[4] = {SCAN_PHASE_CORES, SCAN_PHASE_MERGE, SCAN_PHASE_ATTACH, SCAN_PHASE_CORES};
+  for (int md = 0; md < 3; ++md) {
+    L.evaluated[phase_of_mode[md]] = (int64_t)st[ST_EVAL + md];
+    L.bounded[phase_of_mode[md]] = (int64_t)st[ST_BOUND + md];
+    L.probes[phase_of_mode[md]] = (int64_t)st[ST_PROBES + md];
+  }
+  if (timing) {
+    float ms = 0;
+    for (int ph = 0; ph < SCAN_NUM_PHASES; ++ph) {
+      hipEventElapsedTime(&ms, g->ev[ph], g->ev[ph + 1]);
+      L.ms_phase[ph] = ms;
+    }
+    hipEventElapsedTime(&ms, g->ev[0], g->ev[SCAN_NUM_PHASES]);
+    L.ms_total = ms;
+    for (int k = 0; k < kNumBuckets; ++k) {
+      hipEventElapsedTime(&ms, g->ev[k == 0 ? 1 : SCAN_NUM_PHASES + k], g->ev[SCAN_NUM_PHASES + 1 + k]);
+      L.ms_cores_bucket[k] = ms;
+    }
+  }
+  return SCAN_OK;
+}
+
+int run_counts(scan_graph* g, int32_t* d_counts, hipStream_t s) {
+  const bool timing = g->opts.timing != 0;
+  HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
+  if (timing) hipEventRecord(g->ev[0], s);
+  EdgeArgs A{};
+  A.rp = g->d_rp;
+  A.ci = g->d_ci;
+  A.edges = g->d_edges;
+  A.counts = d_counts;
+  A.stats = g->d_stats;
+  A.p = 1;
+  A.q = 1;
+  A.mu = 2;
+  A.pruning = 0;
+  for (int k = 0; k < kNumBuckets; ++k) {
+    A.e_begin = g->bucket_off[k];
+    A.e_end = g->bucket_off[k + 1];
+    A.bucket = k;
+    launch_edges(s, MODE_COUNTS, k, A);
+  }
+  if (timing) hipEventRecord(g->ev[1], s);
+  HIP_TRY(hipGetLastError(), "kernel launch");
+  unsigned long long st[ST_COUNT];
+  HIP_TRY(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  scan_stats& L = g->last;
+  memset(&L, 0, sizeof(L));
+  L.edges = g->m;
+  L.evaluated[SCAN_PHASE_CORES] = (int64_t)st[ST_EVAL + MODE_COUNTS];
+  L.probes[SCAN_PHASE_CORES] = (int64_t)st[ST_PROBES + MODE_COUNTS];
+  for (int k = 0; k < kNumBuckets; ++k) L.bucket_edges[k] = g->bucket_off[k + 1] - g->bucket_off[k];
+  if (timing) {
+    float ms = 0;
+    hipEventElapsedTime(&ms, g->ev[0], g->ev[1]);
+    L.ms_total = ms;
+    L.ms_phase[SCAN_PHASE_CORES] = ms;
+  }
+  return SCAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void scan_opts_default(scan_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->validate = 1;
+  o->pruning = 1;
+}
+
+const char* scan_last_error(void) { return g_error.c_str(); }
+
+const char* scan_version(void) { return "scan-mi355x 0.1 (gfx950)"; }
+
+int64_t scan_eps_threshold(int64_t p, int64_t q, int64_t a, int64_t b) {
+  if (p < 1 || q < p || a < 1 || b < 1) return -1;
+  const int64_t mx = a > b ? a : b;
+  if ((unsigned __int128)q * (unsigned __int128)mx >= ((unsigned __int128)1 << 32)) return -1;
+  return (int64_t)closed_needed((uint64_t)p, (uint64_t)q, (uint64_t)a, (uint64_t)b);
+}
+
+int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                      const scan_opts* opts, scan_graph** out) {
+  g_error.clear();
+  if (!out) return fail(SCAN_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || nnz < 0) return fail(SCAN_E_INVAL, "n and nnz must be non-negative");
+  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(SCAN_E_INVAL, "row_ptr/col_idx is NULL");
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz)
+    return fail(SCAN_E_GRAPH, "row_ptr must start at 0 and end at nnz");
+  if (nnz % 2 != 0) return fail(SCAN_E_GRAPH, "an undirected CSR has an even number of arcs");
+  scan_graph* g = new (std::nothrow) scan_graph();
+  if (!g) return fail(SCAN_E_NOMEM, "host allocation failed");
+  if (opts) g->opts = *opts;
+  else scan_opts_default(&g->opts);
+  g->n = n;
+  g->nnz = nnz;
+  int rc = SCAN_OK;
+  hipError_t e;
+  LayoutResult lay{};
+#define CTRY(call, what)                         \
+  do {                                           \
+    e = (call);                                  \
+    if (e != hipSuccess) { rc = fail_hip(e, what); goto error; } \
+  } while (0)
+  CTRY(hipGetDevice(&g->device), "hipGetDevice");
+  if (g->opts.hip_stream) {
+    g->stream = (hipStream_t)g->opts.hip_stream;
+  } else {
+    CTRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
+    g->own_stream = true;
+  }
+  if (g->opts.device_budget_bytes && footprint_bytes(n, nnz) > g->opts.device_budget_bytes) {
+    rc = fail(SCAN_E_NOMEM, "graph needs %llu device bytes, budget is %llu",
+              (unsigned long long)footprint_bytes(n, nnz), (unsigned long long)g->opts.device_budget_bytes);
+    goto error;
+  }
+  CTRY(dalloc(&g->d_rp, (int64_t)n + 1), "hipMalloc row_ptr");
+  CTRY(dalloc(&g->d_ci, nnz), "hipMalloc col_idx");
+  CTRY(hipMemcpyAsync(g->d_rp, row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, g->stream),
+       "copy row_ptr");
+  if (nnz > 0)
+    CTRY(hipMemcpyAsync(g->d_ci, col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, g->stream),
+         "copy col_idx");
+  CTRY(build_layout(g->stream, n, nnz, g->d_rp, g->d_ci, g->opts.validate, &g->d_edges, &lay), "layout");
+  if (lay.error) {
+    rc = fail(SCAN_E_GRAPH, "CSR rejected (flags 0x%x: 1 offsets, 2 id range, 4 self-loop, "
+              "8 row order/duplicate, 16 missing reverse arc)", lay.error);
+    goto error;
+  }
+  g->max_degree = lay.max_degree;
+  for (int k = 0; k <= kNumBuckets; ++k) g->bucket_off[k] = lay.bucket_off[k];
+  g->m = lay.bucket_off[kNumBuckets];
+  if (g->opts.validate && g->m * 2 != nnz) {
+    rc = fail(SCAN_E_GRAPH, "edge count %lld does not match nnz/2", (long long)g->m);
+    goto error;
+  }
+  CTRY(dalloc(&g->d_lower, n), "hipMalloc");
+  CTRY(dalloc(&g->d_upper, n), "hipMalloc");
+  CTRY(dalloc(&g->d_role, n), "hipMalloc");
+  CTRY(dalloc(&g->d_parent, n), "hipMalloc");
+  CTRY(dalloc(&g->d_label, n), "hipMalloc");
+  CTRY(dalloc(&g->d_state, g->m), "hipMalloc");
+  CTRY(dalloc(&g->d_stats, ST_COUNT), "hipMalloc");
+  for (auto& ev : g->ev) CTRY(hipEventCreate(&ev), "hipEventCreate");
+  CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+  *out = g;
+  return SCAN_OK;
+error:
+  release(g);
+  delete g;
+#undef CTRY
+  return rc;
+}
+
+int scan_graph_destroy(scan_graph* g) {
+  if (!g) return SCAN_OK;
+  {
+    std::lock_guard<std::mutex> lk(g->lock);
+    hipStreamSynchronize(g->stream);
+    release(g);
+  }
+  delete g;
+  return SCAN_OK;
+}
+
+int scan_graph_info(const scan_graph* g, int32_t* n, int64_t* nnz, int64_t* m, int32_t* max_degree) {
+  if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (m) *m = g->m;
+  if (max_degree) *max_degree = g->max_degree;
+  return SCAN_OK;
+}
+
+int scan_run_device(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu, int32_t* d_labels,
+                    uint8_t* d_roles, void* stream) {
+  g_error.clear();
+  if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
+  if (g->n > 0 && (!d_labels || !d_roles)) return fail(SCAN_E_INVAL, "output pointer is NULL");
+  std::lock_guard<std::mutex> lk(g->lock);
+  hipStream_t s = stream ? (hipStream_t)stream : g->stream;
+  return run_clustering(g, eps_num, eps_den, mu, d_labels, d_roles, s);
+}
+
+int scan_run(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu, int32_t* labels,
+             uint8_t* roles) {
+  g_error.clear();
+  if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
+  if (g->n > 0 && (!labels || !roles)) return fail(SCAN_E_INVAL, "output pointer is NULL");
+  std::lock_guard<std::mutex> lk(g->lock);
+  if (!g->d_out_labels) {
+    HIP_TRY(dalloc(&g->d_out_labels, g->n), "hipMalloc");
+    HIP_TRY(dalloc(&g->d_out_roles, g->n), "hipMalloc");
+  }
+  int rc = run_clustering(g, eps_num, eps_den, mu, g->d_out_labels, g->d_out_roles, g->stream);
+  if (rc != SCAN_OK) return rc;
+  if (g->n > 0) {
+    HIP_TRY(hipMemcpyAsync(labels, g->d_out_labels, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost,
+                           g->stream), "copy labels");
+    HIP_TRY(hipMemcpyAsync(roles, g->d_out_roles, (size_t)g->n, hipMemcpyDeviceToHost, g->stream),
+            "copy roles");
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+  }
+  return SCAN_OK;
+}
+
+int scan_similarity_device(scan_graph* g, int32_t* d_counts, void* stream) {
+  g_error.clear();
+  if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
+  if (g->nnz > 0 && !d_counts) return fail(SCAN_E_INVAL, "counts is NULL");
+  std::lock_guard<std::mutex> lk(g->lock);
+  hipStream_t s = stream ? (hipStream_t)stream : g->stream;
+  return run_counts(g, d_counts, s);
+}
+
+int scan_similarity(scan_graph* g, int32_t* counts) {
+  g_error.clear();
+  if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
+  if (g->nnz > 0 && !counts) return fail(SCAN_E_INVAL, "counts is NULL");
+  std::lock_guard<std::mutex> lk(g->lock);
+  if (g->nnz == 0) return SCAN_OK;
+  if (!g->d_counts) HIP_TRY(dalloc(&g->d_counts, g->nnz), "hipMalloc counts");
+  int rc = run_counts(g, g->d_counts, g->stream);
+  if (rc != SCAN_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(counts, g->d_counts, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost,
+                         g->stream), "copy counts");
+  HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+  return SCAN_OK;
+}
+
+int scan_last_stats(const scan_graph* g, scan_stats* out) {
+  if (!g || !out) return fail(SCAN_E_INVAL, "NULL argument");
+  *out = g->last;
+  return SCAN_OK;
+}
+
+int scan_device_alloc(uint64_t bytes, void** out) {
+  if (!out) return fail(SCAN_E_INVAL, "out is NULL");
+  HIP_TRY(hipMalloc(out, bytes ? bytes : 1), "hipMalloc");
+  return SCAN_OK;
+}
+
+int scan_device_free(void* ptr) {
+  if (ptr) HIP_TRY(hipFree(ptr), "hipFree");
+  return SCAN_OK;
+}
+
+int scan_memcpy_d2h(void* dst, const void* src, uint64_t bytes) {
+  if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+  return SCAN_OK;
+}
+
+int scan_memcpy_h2d(void* dst, const void* src, uint64_t bytes) {
+  if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy H2D");
+  return SCAN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scan {
+
+// Per-vertex role during the run (Table 1 of the paper: ?, C, !C).
+enum : uint8_t { ROLE_UNK = 0, ROLE_CORE = 1, ROLE_NONCORE = 2 };
+// Per-edge similarity state (Table 1: ?, S, !S).
+enum : uint8_t { SIM_UNK = 0, SIM_YES = 1, SIM_NO = 2 };
+
+// Degree buckets of the oriented edge list, keyed by the smaller degree d_s:
+//   0: d_s <= 4, 1: <= 8, 2: <= 16, 3: <= 32, 4: <= 64  (group of 4..64 lanes per edge)
+//   5: d_s > 64                                          (one wave per edge, tiled)
+constexpr int kNumBuckets = 6;
+constexpr int kGroupLanes[5] = {4, 8, 16, 32, 64};
+
+__host__ __device__ inline int bucket_of(int64_t ds) {
+  return ds <= 4 ? 0 : ds <= 8 ? 1 : ds <= 16 ? 2 : ds <= 32 ? 3 : ds <= 64 ? 4 : 5;
+}
+
+// What a pass over the oriented edges does with each edge.
+enum Mode : int {
+  MODE_CORES = 0,   // identifyCore (Alg. 2): similarity test + lower/upper bound counting
+  MODE_MERGE = 1,   // progressive core-core merge (Alg. 3, second loop)
+  MODE_ATTACH = 2,  // border attachment (Alg. 3, last loop), minimum label
+  MODE_COUNTS = 3   // exact closed counts of every edge (no pruning)
+};
+
+// Stats slots (int64 counters on the device).
+enum : int {
+  ST_EVAL = 0,      // + phase: edges intersected
+  ST_BOUND = 4,     // + phase: decided by the degree bound
+  ST_PROBES = 8,    // + phase: smaller-list elements consumed
+  ST_BUCKET_EVAL = 12,   // + bucket (cores phase only)
+  ST_BUCKET_PROBES = 18, // + bucket
+  ST_COUNT = 24
+};
+// Mode -> stats phase slot (0..3).
+__host__ __device__ inline int mode_slot(int mode) { return mode; }
+
+// Smallest closed count c with (c q)^2 >= p^2 a b.  Requires q*max(a,b) < 2^32
+// so that p^2 a b <= q^2 a b < 2^64 and every product below fits in 64 bits.
+__host__ __device__ inline uint32_t closed_needed(uint64_t p, uint64_t q, uint64_t a, uint64_t b) {
+  const uint64_t X = (p * p) * (a * b);
+  uint64_t r = (uint64_t)sqrt((double)X);
+  if (r > 0xFFFFFFFFull) r = 0xFFFFFFFFull;
+  while (r * r > X) --r;
+  while (r < 0xFFFFFFFFull && (r + 1) * (r + 1) <= X) ++r;
+  const uint64_t s = (r * r == X) ? r : r + 1;  // ceil(sqrt(X))
+  return (uint32_t)((s + q - 1) / q);           // (c q)^2 >= X  <=>  c q >= ceil(sqrt(X))
+}
+
+struct EdgeArgs {
+  const int64_t* rp;
+  const int32_t* ci;
+  const int2* edges;  // oriented: x = smaller side (deg, id), y = larger side
+  int64_t e_begin, e_end;
+  uint8_t* state;     // per oriented edge
+  int32_t* lower;     // confirmed |N_eps| lower bound (starts at 1)
+  int32_t* upper;     // |N_eps| upper bound (starts at deg + 1)
+  uint8_t* role;
+  int32_t* parent;
+  int32_t* label;
+  int32_t* counts;    // MODE_COUNTS: per arc output
+  unsigned long long* stats;
+  uint64_t p, q;
+  int32_t mu;
+  int32_t pruning;
+  int32_t bucket;
+};
+
+// Launchers (kernels.hip)
+void launch_init(hipStream_t s, int32_t n, const int64_t* rp, int32_t mu, int32_t* lower,
+                 int32_t* upper, uint8_t* role, int32_t* parent);
+void launch_edges(hipStream_t s, int mode, int bucket, const EdgeArgs& a);
+void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
+void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role);
+void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,
+                 const uint8_t* role, int32_t* parent);
+void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* parent, int32_t* label);
+void launch_output(hipStream_t s, int32_t n, const uint8_t* role, const int32_t* label,
+                   int32_t* out_labels, uint8_t* out_roles);
+
+// Layout (layout.hip)
+struct LayoutResult {
+  int64_t bucket_off[kNumBuckets + 1];
+  int32_t max_degree;
+  int32_t error;  // 0 or bit mask of validation failures
+};
+// Validates the CSR and builds the oriented, bucketed edge list, allocated
+// here (*d_edges, bucket_off[kNumBuckets] entries; caller frees).
+hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* d_rp,
+                        const int32_t* d_ci, int validate, int2** d_edges, LayoutResult* out);
+
+}  // namespace scan

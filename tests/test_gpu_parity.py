@@ -1,0 +1,240 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle: bit-exact
+labels, roles and per-arc closed counts."""
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2311_12281_amd as S
+import pins
+from gpu_helpers import assert_same, gpu_counts, gpu_run, note
+
+pytestmark = pytest.mark.gpu
+
+EPS_ALL = [(1, 10), (1, 5), (1, 3), (1, 2), (2, 3), (3, 4), (4, 5), (1, 1)]
+
+
+def check_graph(g, params, name, counts=True, **opts):
+    note(name, f"n={g.n} m={g.m}", opts)
+    if counts:
+        oc = oracle.counts(g, threads=oracle.max_threads())
+        gc = gpu_counts(g, **opts)
+        assert np.array_equal(gc, oc), f"{name}: closed counts differ at {np.count_nonzero(gc != oc)} arcs"
+    else:
+        oc = None
+    with S.Graph.from_csr(g, **opts) as G:
+        for (p, q), mu in params:
+            note(name, f"eps={p}/{q} mu={mu}")
+            gl, gr = G.run(p, q, mu)
+            if oc is not None:
+                ol, orr = oracle.cluster(g, oc, p, q, mu)
+            else:
+                ol, orr = oracle.scan(g, p, q, mu, threads=oracle.max_threads())
+            assert_same(gl, gr, ol, orr, f"{name} eps={p}/{q} mu={mu}")
+
+
+def test_paper_example():
+    fx = pins.load_paper_example()
+    g = gg.from_edges(fx["n"], fx["edges"])
+    note("paper example")
+    gl, gr = gpu_run(g, *fx["eps"], fx["mu"])
+    assert gr.tolist() == fx["expected_roles"]
+    assert gl.tolist() == fx["expected_labels"]
+    c = gpu_counts(g)
+    k = int(np.searchsorted(g.col_idx[g.row_ptr[0]:g.row_ptr[1]], 1))
+    assert c[g.row_ptr[0] + k] == 5  # (2 + 3) of Example 3.1
+
+
+def test_closed_forms():
+    for n in range(4, 9):
+        note("cycle", n)
+        gl, gr = gpu_run(pins.cycle(n), 2, 3, 3)
+        assert gr.tolist() == [1] * n and gl.tolist() == [0] * n
+        gl, gr = gpu_run(pins.cycle(n), 67, 100, 2)
+        assert gr.tolist() == [0] * n
+    note("K33")
+    gl, gr = gpu_run(pins.complete_bipartite(3, 3), 1, 2, 4)
+    assert gr.tolist() == [1] * 6
+    note("star7")
+    gl, gr = gpu_run(pins.star(7), 1, 2, 3)
+    assert gr.tolist() == [1] + [2] * 7 and gl.tolist() == [0] * 8
+    for n in (2, 5, 70, 130):   # K_70 and K_130 use the one-wave-per-edge kernel
+        note("clique", n)
+        g = pins.complete(n)
+        gl, gr = gpu_run(g, 1, 1, n)
+        assert gr.tolist() == [1] * n and gl.tolist() == [0] * n
+        gl, gr = gpu_run(g, 1, 1, n + 1)
+        assert gr.tolist() == [0] * n
+        assert set(gpu_counts(g).tolist()) == {n}
+
+
+def test_small_graphs_against_oracle():
+    rng = np.random.default_rng(12)
+    cases = []
+    for n in range(1, 6):
+        npairs = n * (n - 1) // 2
+        masks = range(1 << npairs) if npairs <= 6 else rng.choice(1 << npairs, 40, replace=False)
+        for mask in masks:
+            cases.append((n, pins._edges_of(n, int(mask))))
+    for _ in range(60):
+        n = int(rng.integers(6, 13))
+        dens = float(rng.uniform(0.2, 0.8))
+        cases.append((n, [(i, j) for i, j in combinations(range(n), 2) if rng.random() < dens]))
+    note(f"{len(cases)} small graphs")
+    for n, edges in cases:
+        g = gg.from_edges(n, edges)
+        oc = oracle.counts(g)
+        with S.Graph.from_csr(g) as G:
+            assert np.array_equal(G.similarity(), oc), (n, edges)
+            for (p, q) in EPS_ALL[::2]:
+                for mu in (2, 3, 5):
+                    gl, gr = G.run(p, q, mu)
+                    ol, orr = oracle.cluster(g, oc, p, q, mu)
+                    assert_same(gl, gr, ol, orr, f"n={n} edges={edges} eps={p}/{q} mu={mu}")
+
+
+def test_planted_config_A():
+    """Planted partition, n = 10,000 in 50 blocks, p_in 0.15, p_out 0.0005; eps 1/2
+    is degenerate (no similar edge), so 1/5 and 1/10 are added."""
+    g = gg.planted(10000, 50, 0.15, 0.0005, 1)
+    check_graph(g, [((1, 2), 5), ((1, 5), 5), ((1, 10), 5), ((1, 5), 2), ((1, 5), 12)], "planted-A")
+
+
+def test_planted_pruning_off_is_identical():
+    g = gg.planted(10000, 50, 0.15, 0.0005, 1)
+    note("planted pruning on/off")
+    with S.Graph.from_csr(g, pruning=True) as A, S.Graph.from_csr(g, pruning=False) as B:
+        for (p, q), mu in [((1, 5), 5), ((1, 10), 5), ((1, 5), 3)]:
+            la, ra = A.run(p, q, mu)
+            lb, rb = B.run(p, q, mu)
+            assert np.array_equal(ra, rb) and np.array_equal(la, lb)
+
+
+@pytest.mark.parametrize("scale", [14, 16, 18])
+def test_rmat(scale):
+    g = gg.rmat(scale, 16, seed=2)
+    check_graph(g, [((1, 10), 5), ((1, 5), 5), ((1, 2), 5), ((4, 5), 5), ((1, 5), 2), ((1, 10), 3)],
+                f"rmat{scale}")
+
+
+def test_rmat_relabelled():
+    g, _ = gg.permute(gg.rmat(16, 16, seed=2), 3)
+    check_graph(g, [((1, 5), 5), ((1, 10), 3)], "rmat16-permuted")
+
+
+def test_chung_lu():
+    g = gg.chung_lu(200000, 30.0, 2.1, 4000.0, seed=3)
+    check_graph(g, [((1, 10), 3), ((1, 5), 5), ((1, 2), 10)], "chung-lu-200k")
+
+
+def test_repeated_runs_identical():
+    g = gg.rmat(16, 16, seed=5)
+    note("determinism rmat16")
+    with S.Graph.from_csr(g) as G:
+        ref = G.run(1, 10, 3)
+        for _ in range(5):
+            l, r = G.run(1, 10, 3)
+            assert np.array_equal(l, ref[0]) and np.array_equal(r, ref[1])
+
+
+def test_edge_cases():
+    note("empty graph")
+    g0 = gg.from_edges(0, [])
+    with S.Graph.from_csr(g0) as G:
+        l, r = G.run(1, 2, 2)
+        assert l.size == 0 and r.size == 0
+        assert G.similarity().size == 0
+    note("isolated vertices")
+    g1 = gg.from_edges(7, [])
+    l, r = gpu_run(g1, 1, 2, 2)
+    assert l.tolist() == [-1] * 7 and r.tolist() == [0] * 7
+    note("single edge")
+    l, r = gpu_run(gg.from_edges(3, [(0, 2)]), 1, 1, 2)
+    assert l.tolist() == [0, -1, 0] and r.tolist() == [1, 0, 1]
+    note("big star")   # one hub of degree 100,000: skewed pairs in the smallest bucket
+    k = 100000
+    star = gg.from_edges(k + 1, [(0, i) for i in range(1, k + 1)])
+    check_graph(star, [((1, 2), 2), ((1, 500), 2), ((1, 1000), 3)], "star100k")
+    note("two hubs sharing leaves")  # hub-hub edge in the one-wave bucket
+    e = [(0, 1)] + [(0, i) for i in range(2, 3000)] + [(1, i) for i in range(1000, 5000)]
+    check_graph(gg.from_edges(5000, e), [((1, 2), 2), ((1, 10), 3), ((1, 5), 1000)], "two-hubs")
+
+
+def test_invalid_inputs():
+    note("invalid inputs")
+    bad = [
+        (2, np.array([0, 1, 2]), np.array([0, 1])),          # self-loops
+        (3, np.array([0, 2, 3, 4]), np.array([2, 1, 0, 0])),  # unsorted row
+        (3, np.array([0, 2, 3, 4]), np.array([1, 1, 0, 0])),  # duplicate
+        (3, np.array([0, 1, 1, 2]), np.array([1, 0])),        # missing reverse arc
+        (2, np.array([0, 1, 2]), np.array([1, 5])),           # id out of range
+    ]
+    for n, rp, ci in bad:
+        with pytest.raises(S.ScanError) as ei:
+            S.scan_graph_create(n, int(rp[-1]), rp, ci)
+        assert ei.value.code == S.SCAN_E_GRAPH
+    with pytest.raises(S.ScanError) as ei:
+        S.scan_graph_create(2, 2, np.array([0, 1, 3]), np.array([1, 0, 0]))
+    assert ei.value.code == S.SCAN_E_GRAPH
+    g = gg.from_edges(4, [(0, 1), (1, 2)])
+    with S.Graph.from_csr(g) as G:
+        for p, q, mu in [(0, 2, 2), (3, 2, 2), (1, 2, 1)]:
+            with pytest.raises(S.ScanError) as ei:
+                G.run(p, q, mu)
+            assert ei.value.code == S.SCAN_E_INVAL
+        with pytest.raises(S.ScanError) as ei:
+            G.run(1, 2_000_000_000, 2)
+        assert ei.value.code == S.SCAN_E_RANGE
+        l, r = G.run(2, 4, 2)           # eps given unreduced is reduced by gcd
+        l2, r2 = G.run(1, 2, 2)
+        assert np.array_equal(l, l2) and np.array_equal(r, r2)
+
+
+def test_device_entry_points():
+    g = gg.planted(5000, 25, 0.2, 0.001, 7)
+    note("device entry points")
+    with S.Graph.from_csr(g) as G:
+        dl = S.scan_device_alloc(4 * g.n)
+        dr = S.scan_device_alloc(g.n)
+        dc = S.scan_device_alloc(4 * g.nnz)
+        try:
+            G.run_device(1, 5, 4, dl, dr)
+            l = np.empty(g.n, np.int32)
+            r = np.empty(g.n, np.uint8)
+            S.scan_memcpy_d2h(l, dl, 4 * g.n)
+            S.scan_memcpy_d2h(r, dr, g.n)
+            hl, hr = G.run(1, 5, 4)
+            assert np.array_equal(l, hl) and np.array_equal(r, hr)
+            S.scan_similarity_device(G.handle, dc)
+            c = np.empty(g.nnz, np.int32)
+            S.scan_memcpy_d2h(c, dc, 4 * g.nnz)
+            assert np.array_equal(c, G.similarity())
+        finally:
+            for p in (dl, dr, dc):
+                S.scan_device_free(p)
+
+
+def test_stats_are_consistent():
+    g = gg.rmat(16, 16, seed=2)
+    note("stats rmat16")
+    with S.Graph.from_csr(g, timing=True) as G:
+        G.run(1, 5, 5)
+        st = G.stats()
+        assert st["edges"] == g.m
+        assert sum(st["bucket_edges"]) == g.m
+        assert st["ms_total"] > 0
+        assert sum(st["cores_bucket_evaluated"]) == st["evaluated"]["cores"]
+        assert st["evaluated"]["cores"] + st["bounded"]["cores"] <= g.m
+
+
+@pytest.mark.skipif(os.environ.get("SCAN_SKIP_FULL") == "1", reason="full-size case disabled")
+def test_rmat22_full_size():
+    """R-MAT scale 22, edge factor 16: every arc count and every label/role at
+    eps 1/5, 1/2, 4/5 (and 1/10), mu 5, in the launch configuration the
+    benchmark times."""
+    note("rmat22 generate")
+    g = gg.rmat(22, 16, seed=2)
+    check_graph(g, [((1, 5), 5), ((1, 2), 5), ((4, 5), 5), ((1, 10), 5)], "rmat22", timing=True)

@@ -24,7 +24,7 @@ MUTANTS = {
     "core_strict_threshold": ("core[u] = (uint8_t)(ne >= mu);", "core[u] = (uint8_t)(ne > mu);"),
     "bfs_through_non_cores": ("if (sim[i] && core[v] && labels[v] == -1)", "if (sim[i] && labels[v] == -1)"),
     "bfs_ignores_similarity": ("if (sim[i] && core[v] && labels[v] == -1)", "if (core[v] && labels[v] == -1)"),
-    "label_is_last_core": ("labels[v] = s;\n            queue", "labels[v] = x;\n            queue"),
+    "label_is_last_core": ("labels[v] = s;", "labels[v] = x;"),
     "border_max_label": ("labels[u] < best)) best", "labels[u] > best)) best"),
     "border_ignores_similarity": ("if (core[u] && sim[i] && (best", "if (core[u] && (best"),
     "twin_arc_not_written": ("counts[rp[v] + row_find(ci + rp[v], dv, u)] = (int32_t)c;", ""),
