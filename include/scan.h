@@ -62,7 +62,10 @@ typedef struct scan_opts {
                                    result (default); 0: evaluate every edge in full.
                                    Results are identical either way. */
   int32_t timing;               /* 1: record per-phase device times (hipEvents) */
-  int32_t reserved;
+  int32_t strategy;             /* edges whose smaller side has degree > 64:
+                                   0 = grouped by the larger side, whose neighbours are
+                                       staged in an LDS hash table (default);
+                                   1 = one wave per edge, binary search in global memory */
   void* hip_stream;             /* hipStream_t to run on; NULL = a library-owned stream */
 } scan_opts;
 
@@ -72,7 +75,12 @@ void scan_opts_default(scan_opts* opts);
 /*
  * scan_graph_create - copy an undirected CSR graph to the device and build the
  * library's layout (degree-oriented edge list grouped by degree bucket;
- * GPUSCAN++ Section 4.1).
+ * GPUSCAN++ Section 4.1).  If opts->device_budget_bytes is non-zero and the
+ * in-memory layout would exceed it, the graph takes the partition-based path
+ * (GPUSCAN++ Section 5): the CSR stays in pinned host memory, only row_ptr and
+ * the per-vertex state reside on the device, and every run streams blocks of
+ * rows and their edges through buffers that fit the budget.  Results are
+ * identical on both paths.
  *   n        number of vertices, n >= 0
  *   nnz      number of arcs (= 2 |E|)
  *   row_ptr  host int64[n+1], row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
@@ -121,7 +129,8 @@ int scan_run_device(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu,
  */
 int scan_similarity(scan_graph* g, int32_t* counts);
 
-/* scan_similarity with the output in device memory (int32[nnz]). */
+/* scan_similarity with the output in device memory (int32[nnz]); in-memory
+ * graphs only (SCAN_E_INVAL on the partitioned path). */
 int scan_similarity_device(scan_graph* g, int32_t* d_counts, void* stream);
 
 /*
@@ -138,7 +147,7 @@ int64_t scan_eps_threshold(int64_t p, int64_t q, int64_t a, int64_t b);
 enum { SCAN_PHASE_INIT = 0, SCAN_PHASE_CORES, SCAN_PHASE_FINALIZE, SCAN_PHASE_HOOK,
        SCAN_PHASE_MERGE, SCAN_PHASE_FLATTEN, SCAN_PHASE_ATTACH, SCAN_PHASE_OUTPUT,
        SCAN_NUM_PHASES };
-enum { SCAN_NUM_BUCKETS = 6 };
+enum { SCAN_NUM_BUCKETS = 7 };
 typedef struct scan_stats {
   double ms_total;                        /* device time of the whole call */
   double ms_phase[SCAN_NUM_PHASES];       /* device time per phase */
@@ -150,9 +159,98 @@ typedef struct scan_stats {
   int64_t probes[SCAN_NUM_PHASES];        /* smaller-list elements consumed by intersections */
   int64_t cores_bucket_evaluated[SCAN_NUM_BUCKETS];
   int64_t cores_bucket_probes[SCAN_NUM_BUCKETS];
+  int64_t h2d_bytes;                      /* partitioned path: bytes streamed to the device */
 } scan_stats;
 
 int scan_last_stats(const scan_graph* g, scan_stats* out);
+
+/*
+ * Serving: graphs stay resident on the device together with the exact closed
+ * count of every edge (computed once when the graph is added), and
+ * (graph, eps, mu) queries are answered by re-thresholding those counts -
+ * the same result as scan_run, without recomputing any intersection.
+ * Requests are admitted onto `num_slots` slots (one HIP stream and scratch
+ * each) as slots free up, so queries that arrive while others run overlap on
+ * the device.  A graph whose footprint would exceed opts->device_budget_bytes
+ * (0 = no cap) stays in host memory and its queries run through the budgeted
+ * scan_graph_create/scan_run path.  All functions are thread-safe.
+ */
+typedef struct scan_server scan_server;
+
+int scan_server_create(const scan_opts* opts, int32_t num_slots, scan_server** out);
+
+/* Copies the CSR (same requirements as scan_graph_create); *gid_out is the
+ * graph's id for submit/remove. */
+int scan_server_add_graph(scan_server* s, int32_t n, int64_t nnz, const int64_t* row_ptr,
+                          const int32_t* col_idx, int32_t* gid_out);
+
+/* Waits for the graph's queued and running queries, then releases it. */
+int scan_server_remove_graph(scan_server* s, int32_t gid);
+
+/* Queues a query and returns at once with its id in *req_out.
+ * Errors: SCAN_E_INVAL (unknown graph, eps or mu out of range), SCAN_E_RANGE. */
+int scan_server_submit(scan_server* s, int32_t gid, int64_t eps_num, int64_t eps_den, int32_t mu,
+                       int64_t* req_out);
+
+/* Blocks until request `req` has finished, copies its result into
+ * labels[n] / roles[n] (host, caller-owned; either may be NULL) and reports
+ * the time from submit to completion.  Each request is waited for once. */
+int scan_server_wait(scan_server* s, int64_t req, int32_t* labels, uint8_t* roles, double* latency_ms);
+
+/* Device bytes held for resident graphs and slots, graph counts, requests done. */
+int scan_server_info(scan_server* s, uint64_t* resident_bytes, int32_t* graphs, int32_t* resident_graphs,
+                     int64_t* completed);
+
+/* Finishes every queued request, then releases everything. */
+int scan_server_destroy(scan_server* s);
+
+/*
+ * Batched clustering: many independent graphs, each with its own eps and mu,
+ * clustered together.  The graphs are packed into one disjoint union on the
+ * device (every vertex knows its graph and looks up that graph's parameters),
+ * and the whole pipeline for the batch is captured once into a HIP graph, so
+ * one run is a single graph launch whatever the number of graphs.  With
+ * autotune = 1 the library times candidate kernels per degree bucket (lane
+ * group width; LDS-hash or group kernel for the last bucket) on this batch and
+ * keeps the fastest; SCAN_AUTOTUNE_CACHE names an optional file that caches
+ * the choice by batch shape.
+ */
+typedef struct scan_batch {
+  int32_t num_graphs;       /* G >= 0 */
+  const int64_t* vtx_off;   /* [G+1] vertex offsets of the graphs (prefix of n_g), vtx_off[0] = 0 */
+  const int64_t* arc_off;   /* [G+1] arc offsets (prefix of nnz_g), arc_off[0] = 0 */
+  const int64_t* row_ptr;   /* graph g's own row offsets, n_g + 1 entries from 0 to nnz_g,
+                               stored at row_ptr[vtx_off[g] + g] */
+  const int32_t* col_idx;   /* graph g's local neighbour ids (0 <= id < n_g) at col_idx[arc_off[g]] */
+  const int64_t* eps_num;   /* [G] */
+  const int64_t* eps_den;   /* [G] */
+  const int32_t* mu;        /* [G] */
+  int32_t autotune;         /* 1: choose the per-bucket kernels by timing them on this batch */
+} scan_batch;
+
+typedef struct scan_batch_graph scan_batch_graph;
+
+/* Packs and validates the batch (each graph as in scan_graph_create), builds
+ * the device layout, optionally autotunes, and captures the run. */
+int scan_batch_create(const scan_batch* b, const scan_opts* opts, scan_batch_graph** out);
+
+/* Clusters every graph of the batch: labels[vtx_off[G]] receive graph-local
+ * labels (minimum core id within the graph, -1 if unclassified) and roles the
+ * roles, both host, caller-owned, packed like the vertices.  replay = 1 runs
+ * the captured HIP graph, 0 issues the same kernels one by one. */
+int scan_batch_run(scan_batch_graph* bg, int32_t replay, int32_t* labels, uint8_t* roles);
+
+/* Chosen kernel per bucket: lanes[SCAN_NUM_BUCKETS] lane-group widths, *hub =
+ * 1 if the last bucket uses the LDS-hash kernel. */
+int scan_batch_config(const scan_batch_graph* bg, int32_t* lanes, int32_t* hub);
+
+/* Statistics of the last scan_batch_run. */
+int scan_batch_stats(const scan_batch_graph* bg, scan_stats* out);
+
+int scan_batch_destroy(scan_batch_graph* bg);
+
+/* One-shot: create, run once, destroy. */
+int scan_run_batch(const scan_batch* b, const scan_opts* opts, int32_t* labels, uint8_t* roles);
 
 /* Device memory helpers for the *_device entry points (hipMalloc/hipFree/hipMemcpy). */
 int scan_device_alloc(uint64_t bytes, void** out);

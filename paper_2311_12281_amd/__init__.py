@@ -23,12 +23,16 @@ SCAN_OK, SCAN_E_INVAL, SCAN_E_GRAPH, SCAN_E_RANGE, SCAN_E_NOMEM, SCAN_E_DEVICE =
 SCAN_UNCLASSIFIED, SCAN_CORE, SCAN_BORDER = 0, 1, 2
 PHASES = ["init", "cores", "finalize", "hook", "merge", "flatten", "attach", "output"]
 NUM_PHASES = len(PHASES)
-NUM_BUCKETS = 6
+NUM_BUCKETS = 7
 EXPORTED = [
     "scan_opts_default", "scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
     "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_eps_threshold",
     "scan_last_stats", "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h",
     "scan_memcpy_h2d", "scan_last_error", "scan_version",
+    "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph", "scan_server_submit",
+    "scan_server_wait", "scan_server_info", "scan_server_destroy",
+    "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
+    "scan_run_batch",
 ]
 
 
@@ -48,8 +52,22 @@ class scan_opts(ctypes.Structure):
         ("validate", ctypes.c_int32),
         ("pruning", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("strategy", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class scan_batch(ctypes.Structure):
+    _fields_ = [
+        ("num_graphs", ctypes.c_int32),
+        ("vtx_off", ctypes.c_void_p),
+        ("arc_off", ctypes.c_void_p),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("eps_num", ctypes.c_void_p),
+        ("eps_den", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -65,6 +83,7 @@ class scan_stats(ctypes.Structure):
         ("probes", ctypes.c_int64 * NUM_PHASES),
         ("cores_bucket_evaluated", ctypes.c_int64 * NUM_BUCKETS),
         ("cores_bucket_probes", ctypes.c_int64 * NUM_BUCKETS),
+        ("h2d_bytes", ctypes.c_int64),
     ]
 
 
@@ -97,11 +116,28 @@ def lib():
         L.scan_device_free.argtypes = [vp]
         L.scan_memcpy_d2h.argtypes = [vp, vp, u64]
         L.scan_memcpy_h2d.argtypes = [vp, vp, u64]
+        L.scan_server_create.argtypes = [P(scan_opts), i32, P(vp)]
+        L.scan_server_add_graph.argtypes = [vp, i32, i64, vp, vp, P(i32)]
+        L.scan_server_remove_graph.argtypes = [vp, i32]
+        L.scan_server_submit.argtypes = [vp, i32, i64, i64, i32, P(i64)]
+        L.scan_server_wait.argtypes = [vp, i64, vp, vp, P(ctypes.c_double)]
+        L.scan_server_info.argtypes = [vp, P(u64), P(i32), P(i32), P(i64)]
+        L.scan_server_destroy.argtypes = [vp]
+        L.scan_batch_create.argtypes = [P(scan_batch), P(scan_opts), P(vp)]
+        L.scan_batch_run.argtypes = [vp, i32, vp, vp]
+        L.scan_batch_config.argtypes = [vp, vp, P(i32)]
+        L.scan_batch_stats.argtypes = [vp, P(scan_stats)]
+        L.scan_batch_destroy.argtypes = [vp]
+        L.scan_run_batch.argtypes = [P(scan_batch), P(scan_opts), vp, vp]
         L.scan_last_error.restype = ctypes.c_char_p
         L.scan_version.restype = ctypes.c_char_p
         for name in ("scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
                      "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_last_stats",
-                     "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h", "scan_memcpy_h2d"):
+                     "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h", "scan_memcpy_h2d",
+                     "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph",
+                     "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
+                     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
+                     "scan_batch_destroy", "scan_run_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -131,8 +167,9 @@ def scan_opts_default() -> scan_opts:
 
 
 def make_opts(budget: int = 0, validate: bool = True, pruning: bool = True, timing: bool = False,
-              stream: int | None = None) -> scan_opts:
+              strategy: int = 0, stream: int | None = None) -> scan_opts:
     o = scan_opts_default()
+    o.strategy = int(strategy)
     o.device_budget_bytes = int(budget)
     o.validate = int(bool(validate))
     o.pruning = int(bool(pruning))
@@ -211,6 +248,7 @@ def scan_last_stats(g) -> dict:
         "probes": dict(zip(PHASES, list(s.probes))),
         "cores_bucket_evaluated": list(s.cores_bucket_evaluated),
         "cores_bucket_probes": list(s.cores_bucket_probes),
+        "h2d_bytes": s.h2d_bytes,
     }
 
 
@@ -278,3 +316,181 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Serving
+
+def scan_server_create(opts: scan_opts | None = None, num_slots: int = 4) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().scan_server_create(ctypes.byref(opts) if opts is not None else None, int(num_slots),
+                                    ctypes.byref(h)))
+    return h
+
+
+def scan_server_add_graph(s, n: int, nnz: int, row_ptr: np.ndarray, col_idx: np.ndarray) -> int:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    gid = ctypes.c_int32()
+    _check(lib().scan_server_add_graph(s, int(n), int(nnz), _vp(rp), _vp(ci) if nnz else None,
+                                       ctypes.byref(gid)))
+    return gid.value
+
+
+def scan_server_remove_graph(s, gid: int) -> None:
+    _check(lib().scan_server_remove_graph(s, int(gid)))
+
+
+def scan_server_submit(s, gid: int, eps_num: int, eps_den: int, mu: int) -> int:
+    req = ctypes.c_int64()
+    _check(lib().scan_server_submit(s, int(gid), int(eps_num), int(eps_den), int(mu), ctypes.byref(req)))
+    return req.value
+
+
+def scan_server_wait(s, req: int, n: int):
+    labels = np.empty(max(n, 1), dtype=np.int32)
+    roles = np.empty(max(n, 1), dtype=np.uint8)
+    lat = ctypes.c_double()
+    _check(lib().scan_server_wait(s, int(req), _vp(labels), _vp(roles), ctypes.byref(lat)))
+    return labels[:n], roles[:n], lat.value
+
+
+def scan_server_info(s) -> dict:
+    rb, ng, nr, done = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().scan_server_info(s, ctypes.byref(rb), ctypes.byref(ng), ctypes.byref(nr), ctypes.byref(done)))
+    return {"resident_bytes": rb.value, "graphs": ng.value, "resident_graphs": nr.value,
+            "completed": done.value}
+
+
+def scan_server_destroy(s) -> None:
+    _check(lib().scan_server_destroy(s))
+
+
+class Server:
+    """Owning wrapper around a scan_server handle."""
+
+    def __init__(self, num_slots: int = 4, budget: int = 0, **opts):
+        self.handle = scan_server_create(make_opts(budget=budget, **opts), num_slots)
+        self.sizes = {}
+
+    def add(self, g) -> int:
+        gid = scan_server_add_graph(self.handle, g.n, g.nnz, g.row_ptr, g.col_idx)
+        self.sizes[gid] = g.n
+        return gid
+
+    def remove(self, gid: int) -> None:
+        scan_server_remove_graph(self.handle, gid)
+        self.sizes.pop(gid, None)
+
+    def submit(self, gid: int, p: int, q: int, mu: int) -> int:
+        return scan_server_submit(self.handle, gid, p, q, mu)
+
+    def wait(self, req: int, gid: int):
+        return scan_server_wait(self.handle, req, self.sizes[gid])
+
+    def info(self) -> dict:
+        return scan_server_info(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            scan_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Batched
+
+def pack_batch(graphs, eps, mus):
+    """Packs CSR graphs (objects with n, row_ptr, col_idx) and per-graph
+    parameters into the arrays of struct scan_batch.  Returns (arrays, struct);
+    keep `arrays` alive while the struct is used."""
+    G = len(graphs)
+    vtx_off = np.zeros(G + 1, np.int64)
+    arc_off = np.zeros(G + 1, np.int64)
+    for k, g in enumerate(graphs):
+        vtx_off[k + 1] = vtx_off[k] + g.n
+        arc_off[k + 1] = arc_off[k] + int(g.row_ptr[-1])
+    row_ptr = np.concatenate([np.asarray(g.row_ptr, np.int64) for g in graphs]) if G else np.zeros(1, np.int64)
+    col_idx = np.concatenate([np.asarray(g.col_idx, np.int32) for g in graphs]) if G else np.zeros(1, np.int32)
+    if col_idx.size == 0:
+        col_idx = np.zeros(1, np.int32)
+    eps_num = np.array([e[0] for e in eps], np.int64)
+    eps_den = np.array([e[1] for e in eps], np.int64)
+    mu = np.array(mus, np.int32)
+    arrays = dict(vtx_off=vtx_off, arc_off=arc_off, row_ptr=row_ptr, col_idx=col_idx, eps_num=eps_num,
+                  eps_den=eps_den, mu=mu)
+    st = scan_batch(G, *(ctypes.c_void_p(arrays[k].ctypes.data) for k in
+                         ("vtx_off", "arc_off", "row_ptr", "col_idx", "eps_num", "eps_den", "mu")), 0)
+    return arrays, st
+
+
+class Batch:
+    """Owning wrapper around a scan_batch_graph handle."""
+
+    def __init__(self, graphs, eps, mus, autotune: bool = False, **opts):
+        self.arrays, st = pack_batch(graphs, eps, mus)
+        st.autotune = int(bool(autotune))
+        self.N = int(self.arrays["vtx_off"][-1])
+        self.vtx_off = self.arrays["vtx_off"]
+        o = make_opts(**opts)
+        self.handle = ctypes.c_void_p()
+        _check(lib().scan_batch_create(ctypes.byref(st), ctypes.byref(o), ctypes.byref(self.handle)))
+
+    def run(self, replay: bool = True):
+        labels = np.empty(max(self.N, 1), np.int32)
+        roles = np.empty(max(self.N, 1), np.uint8)
+        _check(lib().scan_batch_run(self.handle, int(bool(replay)), _vp(labels), _vp(roles)))
+        return labels[:self.N], roles[:self.N]
+
+    def split(self, arr):
+        return [arr[self.vtx_off[k]:self.vtx_off[k + 1]] for k in range(len(self.vtx_off) - 1)]
+
+    def config(self):
+        lanes = np.zeros(NUM_BUCKETS, np.int32)
+        hub = ctypes.c_int32()
+        _check(lib().scan_batch_config(self.handle, _vp(lanes), ctypes.byref(hub)))
+        return lanes.tolist(), bool(hub.value)
+
+    def stats(self):
+        s = scan_stats()
+        _check(lib().scan_batch_stats(self.handle, ctypes.byref(s)))
+        return {"ms_total": s.ms_total, "evaluated_cores": s.evaluated[1], "edges": s.edges}
+
+    def close(self):
+        if self.handle is not None:
+            _check(lib().scan_batch_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def scan_run_batch(graphs, eps, mus, **opts):
+    arrays, st = pack_batch(graphs, eps, mus)
+    N = int(arrays["vtx_off"][-1])
+    labels = np.empty(max(N, 1), np.int32)
+    roles = np.empty(max(N, 1), np.uint8)
+    o = make_opts(**opts)
+    _check(lib().scan_run_batch(ctypes.byref(st), ctypes.byref(o), _vp(labels), _vp(roles)))
+    return labels[:N], roles[:N]

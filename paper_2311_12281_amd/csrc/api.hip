@@ -1,20 +1,23 @@
 // C-ABI of the library (declared in include/scan.h): graph creation, the
 // in-memory clustering run (GPUSCAN++ Algorithm 1 with Algorithms 2-3), the
 // exact per-arc closed counts, statistics and small device-memory helpers.
-#include "scan_internal.h"
-#include "../../include/scan.h"
+#include "graph.h"
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
-#include <mutex>
-#include <string>
-
-using namespace scan;
 
 namespace {
-
 thread_local std::string g_error;
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+}  // namespace
+
+namespace scan {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -32,52 +35,15 @@ int fail_hip(hipError_t e, const char* what) {
   return fail(SCAN_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(call, what)                   \
-  do {                                        \
-    hipError_t _e = (call);                   \
-    if (_e != hipSuccess) return fail_hip(_e, what); \
-  } while (0)
+}  // namespace scan
 
-int64_t gcd64(int64_t a, int64_t b) {
-  while (b) { int64_t t = a % b; a = b; b = t; }
-  return a;
-}
 
-}  // namespace
-
-struct scan_graph {
-  int32_t n = 0;
-  int64_t nnz = 0, m = 0;
-  int32_t max_degree = 0;
-  int64_t bucket_off[kNumBuckets + 1] = {0};
-  scan_opts opts{};
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-  // graph (read-only after create)
-  int64_t* d_rp = nullptr;
-  int32_t* d_ci = nullptr;
-  int2* d_edges = nullptr;
-  // per-run state
-  int32_t* d_lower = nullptr;
-  int32_t* d_upper = nullptr;
-  uint8_t* d_role = nullptr;
-  int32_t* d_parent = nullptr;
-  int32_t* d_label = nullptr;
-  uint8_t* d_state = nullptr;
-  unsigned long long* d_stats = nullptr;
-  int32_t* d_out_labels = nullptr;  // staging for the host-output entry points
-  uint8_t* d_out_roles = nullptr;
-  int32_t* d_counts = nullptr;      // staging for scan_similarity
-  hipEvent_t ev[SCAN_NUM_PHASES + kNumBuckets + 2] = {};
-  std::mutex lock;
-  scan_stats last{};
-};
 
 namespace {
 
 void release(scan_graph* g) {
-  void* ptrs[] = {g->d_rp, g->d_ci, g->d_edges, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+  part_release(g);
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_edges, g->d_jobs, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -91,31 +57,35 @@ hipError_t dalloc(T** p, int64_t count) {
   return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
 }
 
-uint64_t footprint_bytes(int32_t n, int64_t nnz) {
-  const uint64_t m = (uint64_t)nnz / 2;
-  return 8ull * (n + 1) + 4ull * nnz + 8ull * m + 1ull * m + 22ull * n + 8ull * 64;
+
+constexpr int kCounters = 4;
+
+}  // namespace
+
+// One pass of `mode` over bucket k of the oriented edges.
+void scan::launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunConfig* cfg) {
+  A.e_begin = g->bucket_off[k];
+  A.e_end = g->bucket_off[k + 1];
+  A.bucket = k;
+  const bool hub = cfg ? cfg->hub : g->opts.strategy == 0;
+  if (k == kNumBuckets - 1 && hub && g->hub_jobs > 0)
+    launch_hub(s, mode, A, g->d_jobs, g->hub_jobs, g->d_counters + mode, g->d_worklist);
+  else if (cfg && cfg->lanes[k] > 0)
+    launch_edges_lanes(s, mode, cfg->lanes[k], A);
+  else
+    launch_edges(s, mode, k, A);
 }
 
-// Runs Algorithm 1 (with Algorithms 2 and 3) on g; outputs into device buffers.
-int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
-                   uint8_t* d_roles, hipStream_t s) {
-  if (p < 1 || q < p) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den (got %lld/%lld)",
-                                  (long long)p, (long long)q);
-  if (mu < 2) return fail(SCAN_E_INVAL, "mu must be >= 2 (got %d)", mu);
-  const int64_t gd = gcd64(p, q);
-  p /= gd;
-  q /= gd;
-  if ((unsigned __int128)q * (unsigned __int128)((uint64_t)g->max_degree + 1) >= ((unsigned __int128)1 << 32))
-    return fail(SCAN_E_RANGE, "eps denominator %lld with max degree %d exceeds the 64-bit test range",
-                (long long)q, g->max_degree);
-  const bool timing = g->opts.timing != 0;
+// Enqueues Algorithm 1 (with Algorithms 2 and 3) on g: kernel launches only
+// (no memset, copy or synchronisation), so that it can be captured in a HIP
+// graph.  Per-graph parameters come from A.gid/gp/gq/gmu when set.
+void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
+                              const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg) {
   const int n = g->n;
   const int64_t m = g->m;
-  HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
   auto mark = [&](int k) {
-    if (timing) hipEventRecord(g->ev[k], s);
+    if (timing) (void)hipEventRecord(g->ev[k], s);
   };
-  EdgeArgs A{};
   A.rp = g->d_rp;
   A.ci = g->d_ci;
   A.edges = g->d_edges;
@@ -126,47 +96,38 @@ int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_l
   A.parent = g->d_parent;
   A.label = g->d_label;
   A.counts = nullptr;
+  A.edge_counts = nullptr;
   A.stats = g->d_stats;
-  A.p = (uint64_t)p;
-  A.q = (uint64_t)q;
-  A.mu = mu;
-  A.pruning = g->opts.pruning;
   // Events: 0 start, then the end of each phase; the cores phase also marks
   // the end of each bucket (slots SCAN_NUM_PHASES + 1 + k).
   mark(0);
-  launch_init(s, n, g->d_rp, mu, g->d_lower, g->d_upper, g->d_role, g->d_parent);
+  launch_zero_u64(s, g->d_stats, ST_COUNT);
+  launch_init(s, n, g->d_rp, A.mu, g->d_lower, g->d_upper, g->d_role, g->d_parent, A.gid, A.gmu);
   launch_fill_u8(s, g->d_state, m, SIM_UNK);
+  launch_zero_u64(s, g->d_counters, kCounters);
   mark(1);
   for (int k = 0; k < kNumBuckets; ++k) {
-    A.e_begin = g->bucket_off[k];
-    A.e_end = g->bucket_off[k + 1];
-    A.bucket = k;
-    launch_edges(s, MODE_CORES, k, A);
+    launch_bucket(g, s, MODE_CORES, k, A, cfg);
     mark(SCAN_NUM_PHASES + 1 + k);
   }
   mark(2);
-  launch_finalize_roles(s, n, mu, g->d_lower, g->d_role);
+  launch_finalize_roles(s, n, A.mu, g->d_lower, g->d_role, A.gid, A.gmu);
   mark(3);
   launch_hook(s, m, g->d_edges, g->d_state, g->d_role, g->d_parent);
   mark(4);
-  for (int k = 0; k < kNumBuckets; ++k) {
-    A.e_begin = g->bucket_off[k];
-    A.e_end = g->bucket_off[k + 1];
-    A.bucket = k;
-    launch_edges(s, MODE_MERGE, k, A);
-  }
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_MERGE, k, A, cfg);
   mark(5);
   launch_flatten(s, n, g->d_role, g->d_parent, g->d_label);
   mark(6);
-  for (int k = 0; k < kNumBuckets; ++k) {
-    A.e_begin = g->bucket_off[k];
-    A.e_end = g->bucket_off[k + 1];
-    A.bucket = k;
-    launch_edges(s, MODE_ATTACH, k, A);
-  }
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_ATTACH, k, A, cfg);
   mark(7);
-  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles);
+  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles, A.gid, gbase);
   mark(8);
+}
+
+// Reads the statistics counters and event times of the last enqueued run.
+int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
+  const int64_t m = g->m;
   HIP_TRY(hipGetLastError(), "kernel launch");
   unsigned long long st[ST_COUNT];
   HIP_TRY(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
@@ -201,26 +162,51 @@ int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_l
   return SCAN_OK;
 }
 
-int run_counts(scan_graph* g, int32_t* d_counts, hipStream_t s) {
+namespace {
+
+// Validates eps and mu and runs the in-memory or partitioned clustering.
+int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
+                   uint8_t* d_roles, hipStream_t s) {
+  if (p < 1 || q < p) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den (got %lld/%lld)",
+                                  (long long)p, (long long)q);
+  if (mu < 2) return fail(SCAN_E_INVAL, "mu must be >= 2 (got %d)", mu);
+  if (g->opts.strategy < 0 || g->opts.strategy > 1) return fail(SCAN_E_INVAL, "unknown strategy %d", g->opts.strategy);
+  const int64_t gd = gcd64(p, q);
+  p /= gd;
+  q /= gd;
+  if ((unsigned __int128)q * (unsigned __int128)((uint64_t)g->max_degree + 1) >= ((unsigned __int128)1 << 32))
+    return fail(SCAN_E_RANGE, "eps denominator %lld with max degree %d exceeds the 64-bit test range",
+                (long long)q, g->max_degree);
+  if (g->partitioned) return part_run(g, (uint64_t)p, (uint64_t)q, mu, d_labels, d_roles, s);
+  EdgeArgs A{};
+  A.p = (uint64_t)p;
+  A.q = (uint64_t)q;
+  A.mu = mu;
+  A.pruning = g->opts.pruning;
+  const bool timing = g->opts.timing != 0;
+  enqueue_clustering(g, A, d_labels, d_roles, nullptr, s, timing, nullptr);
+  return collect_stats(g, s, timing);
+}
+
+}  // namespace
+
+int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hipStream_t s) {
   const bool timing = g->opts.timing != 0;
   HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
+  launch_zero_u64(s, g->d_counters, kCounters);
   if (timing) hipEventRecord(g->ev[0], s);
   EdgeArgs A{};
   A.rp = g->d_rp;
   A.ci = g->d_ci;
   A.edges = g->d_edges;
-  A.counts = d_counts;
+  A.counts = d_counts_arc;
+  A.edge_counts = d_counts_edge;
   A.stats = g->d_stats;
   A.p = 1;
   A.q = 1;
   A.mu = 2;
   A.pruning = 0;
-  for (int k = 0; k < kNumBuckets; ++k) {
-    A.e_begin = g->bucket_off[k];
-    A.e_end = g->bucket_off[k + 1];
-    A.bucket = k;
-    launch_edges(s, MODE_COUNTS, k, A);
-  }
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_COUNTS, k, A);
   if (timing) hipEventRecord(g->ev[1], s);
   HIP_TRY(hipGetLastError(), "kernel launch");
   unsigned long long st[ST_COUNT];
@@ -240,8 +226,6 @@ int run_counts(scan_graph* g, int32_t* d_counts, hipStream_t s) {
   }
   return SCAN_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -294,10 +278,27 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     CTRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
     g->own_stream = true;
   }
-  if (g->opts.device_budget_bytes && footprint_bytes(n, nnz) > g->opts.device_budget_bytes) {
-    rc = fail(SCAN_E_NOMEM, "graph needs %llu device bytes, budget is %llu",
-              (unsigned long long)footprint_bytes(n, nnz), (unsigned long long)g->opts.device_budget_bytes);
-    goto error;
+  if (g->opts.device_budget_bytes && inmemory_footprint(n, nnz) > g->opts.device_budget_bytes) {
+    // Partition-based path: the CSR stays in pinned host memory.
+    rc = part_validate(n, nnz, row_ptr, col_idx, g->opts.validate != 0);
+    if (rc != SCAN_OK) goto error;
+    for (int32_t v = 0; v < n; ++v)
+      g->max_degree = (int32_t)std::max<int64_t>(g->max_degree, row_ptr[v + 1] - row_ptr[v]);
+    rc = part_create(g, row_ptr, col_idx, g->opts.device_budget_bytes);
+    if (rc != SCAN_OK) goto error;
+    CTRY(dalloc(&g->d_rp, (int64_t)n + 1), "hipMalloc row_ptr");
+    CTRY(hipMemcpyAsync(g->d_rp, row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, g->stream),
+         "copy row_ptr");
+    CTRY(dalloc(&g->d_lower, n), "hipMalloc");
+    CTRY(dalloc(&g->d_upper, n), "hipMalloc");
+    CTRY(dalloc(&g->d_role, n), "hipMalloc");
+    CTRY(dalloc(&g->d_parent, n), "hipMalloc");
+    CTRY(dalloc(&g->d_label, n), "hipMalloc");
+    CTRY(dalloc(&g->d_stats, ST_COUNT), "hipMalloc");
+    for (auto& ev : g->ev) CTRY(hipEventCreate(&ev), "hipEventCreate");
+    CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    *out = g;
+    return SCAN_OK;
   }
   CTRY(dalloc(&g->d_rp, (int64_t)n + 1), "hipMalloc row_ptr");
   CTRY(dalloc(&g->d_ci, nnz), "hipMalloc col_idx");
@@ -306,13 +307,15 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
   if (nnz > 0)
     CTRY(hipMemcpyAsync(g->d_ci, col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, g->stream),
          "copy col_idx");
-  CTRY(build_layout(g->stream, n, nnz, g->d_rp, g->d_ci, g->opts.validate, &g->d_edges, &lay), "layout");
+  CTRY(build_layout(g->stream, n, nnz, row_ptr, col_idx, g->d_rp, g->d_ci, g->opts.validate, &g->d_edges,
+                    &g->d_jobs, &lay), "layout");
   if (lay.error) {
     rc = fail(SCAN_E_GRAPH, "CSR rejected (flags 0x%x: 1 offsets, 2 id range, 4 self-loop, "
-              "8 row order/duplicate, 16 missing reverse arc)", lay.error);
+              "8 row order/duplicate, 16 missing reverse arc, 32 inconsistent layout)", lay.error);
     goto error;
   }
   g->max_degree = lay.max_degree;
+  g->hub_jobs = lay.hub_jobs;
   for (int k = 0; k <= kNumBuckets; ++k) g->bucket_off[k] = lay.bucket_off[k];
   g->m = lay.bucket_off[kNumBuckets];
   if (g->opts.validate && g->m * 2 != nnz) {
@@ -326,6 +329,8 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
   CTRY(dalloc(&g->d_label, n), "hipMalloc");
   CTRY(dalloc(&g->d_state, g->m), "hipMalloc");
   CTRY(dalloc(&g->d_stats, ST_COUNT), "hipMalloc");
+  CTRY(dalloc(&g->d_counters, kCounters), "hipMalloc");
+  CTRY(dalloc(&g->d_worklist, g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]), "hipMalloc");
   for (auto& ev : g->ev) CTRY(hipEventCreate(&ev), "hipEventCreate");
   CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
   *out = g;
@@ -394,8 +399,9 @@ int scan_similarity_device(scan_graph* g, int32_t* d_counts, void* stream) {
   if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
   if (g->nnz > 0 && !d_counts) return fail(SCAN_E_INVAL, "counts is NULL");
   std::lock_guard<std::mutex> lk(g->lock);
+  if (g->partitioned) return fail(SCAN_E_INVAL, "device output is not available on the partitioned path");
   hipStream_t s = stream ? (hipStream_t)stream : g->stream;
-  return run_counts(g, d_counts, s);
+  return run_counts(g, d_counts, nullptr, s);
 }
 
 int scan_similarity(scan_graph* g, int32_t* counts) {
@@ -404,8 +410,9 @@ int scan_similarity(scan_graph* g, int32_t* counts) {
   if (g->nnz > 0 && !counts) return fail(SCAN_E_INVAL, "counts is NULL");
   std::lock_guard<std::mutex> lk(g->lock);
   if (g->nnz == 0) return SCAN_OK;
+  if (g->partitioned) return part_counts(g, counts, g->stream);
   if (!g->d_counts) HIP_TRY(dalloc(&g->d_counts, g->nnz), "hipMalloc counts");
-  int rc = run_counts(g, g->d_counts, g->stream);
+  int rc = run_counts(g, g->d_counts, nullptr, g->stream);
   if (rc != SCAN_OK) return rc;
   HIP_TRY(hipMemcpyAsync(counts, g->d_counts, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost,
                          g->stream), "copy counts");

@@ -1,0 +1,121 @@
+// Internal: the graph object behind the opaque scan_graph handle, error
+// reporting, and entry points shared by the C-ABI translation units.
+#pragma once
+
+#include "scan_internal.h"
+#include "../../include/scan.h"
+
+#include <mutex>
+#include <string>
+
+using namespace scan;
+
+// Partitioned (out-of-core) layout: GPUSCAN++ Section 5 (Def. 5.1, Lemma 5.1,
+// Alg. 5).  The CSR stays in pinned host memory; vertex ranges ("blocks")
+// are sized so that two blocks' rows fit the device row buffer, and every
+// edge belongs to the pair of blocks of its endpoints.  A chunk is a run of
+// one pair's edges (grouped by degree bucket) small enough for the device
+// edge buffer.
+struct PartChunk {
+  int32_t bi, bj;                          // block pair, bi <= bj
+  int64_t begin, end;                      // range of the pinned edge array
+  int64_t bucket_off[kNumBuckets + 1];     // bucket sub-ranges, clipped to [begin, end)
+};
+
+struct PartPlan {
+  std::vector<int32_t> block_lo;  // K+1 vertex boundaries
+  std::vector<int64_t> h_rp;      // host copy of row_ptr
+  std::vector<PartChunk> chunks;
+  int32_t* h_ci = nullptr;        // pinned copy of col_idx
+  int2* h_edges = nullptr;        // pinned: oriented edges ordered by (pair, bucket, arc)
+  uint8_t* h_state = nullptr;     // pinned: edge states, streamed with the edges
+  int32_t* h_ecount = nullptr;    // pinned: per-edge closed counts (scan_similarity)
+  int64_t row_cap = 0;            // ints of the device row buffer (two blocks)
+  int64_t chunk_cap = 0;          // edges per chunk
+  int32_t* d_rows = nullptr;
+  int2* d_edges = nullptr;
+  uint8_t* d_state = nullptr;
+  int32_t* d_ecount = nullptr;
+  uint64_t h2d_bytes = 0;         // bytes sent to the device by the last call
+};
+
+struct scan_graph {
+  bool partitioned = false;
+  PartPlan part;
+  int32_t n = 0;
+  int64_t nnz = 0, m = 0;
+  int32_t max_degree = 0;
+  int64_t bucket_off[kNumBuckets + 1] = {0};
+  scan_opts opts{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  // graph (read-only after create)
+  int64_t* d_rp = nullptr;
+  int32_t* d_ci = nullptr;
+  int2* d_edges = nullptr;
+  HubJob* d_jobs = nullptr;
+  int64_t hub_jobs = 0;
+  int32_t* d_worklist = nullptr;  // one slot per edge of the last bucket
+  // per-run state
+  int32_t* d_lower = nullptr;
+  int32_t* d_upper = nullptr;
+  uint8_t* d_role = nullptr;
+  int32_t* d_parent = nullptr;
+  int32_t* d_label = nullptr;
+  uint8_t* d_state = nullptr;
+  unsigned long long* d_stats = nullptr;
+  unsigned long long* d_counters = nullptr;  // job counters of the LDS-hash kernel, one per pass
+  int32_t* d_out_labels = nullptr;  // staging for the host-output entry points
+  uint8_t* d_out_roles = nullptr;
+  int32_t* d_counts = nullptr;      // staging for scan_similarity
+  hipEvent_t ev[SCAN_NUM_PHASES + kNumBuckets + 2] = {};
+  std::mutex lock;
+  scan_stats last{};
+};
+
+namespace scan {
+
+// Per-bucket kernel choice for one run: lanes[k] = lane-group width of the
+// group kernel for bucket k (0 = the bucket's default), hub = LDS-hash kernel
+// for the last bucket.
+struct RunConfig {
+  int lanes[kNumBuckets];
+  bool hub;
+};
+
+void launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunConfig* cfg = nullptr);
+// Kernel launches of one clustering run (capturable); A carries eps/mu (or
+// per-graph arrays); gbase (batch) turns labels into graph-local ids.
+void enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
+                        const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg);
+int collect_stats(scan_graph* g, hipStream_t s, bool timing);
+
+// Sets the thread-local message returned by scan_last_error; returns code.
+int fail(int code, const char* fmt, ...);
+int fail_hip(hipError_t e, const char* what);
+
+// Exact closed counts of every edge of g on stream s, written per arc
+// (d_counts_arc, CSR order) and/or per oriented edge (d_counts_edge); either
+// may be null.
+int run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hipStream_t s);
+
+// Partitioned path (partition.hip).  device bytes the in-memory layout needs:
+uint64_t inmemory_footprint(int32_t n, int64_t nnz);
+// Plans blocks and chunks for `budget` device bytes, copies the CSR to pinned
+// memory and allocates the resident state and streaming buffers.
+int part_validate(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, bool full);
+int part_create(scan_graph* g, const int64_t* row_ptr, const int32_t* col_idx, uint64_t budget);
+void part_release(scan_graph* g);
+int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_labels, uint8_t* d_roles,
+             hipStream_t s);
+// Exact per-arc closed counts into host memory (CSR order).
+int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s);
+
+}  // namespace scan
+
+#define HIP_TRY(call, what)                             \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return scan::fail_hip(_e, what); \
+  } while (0)

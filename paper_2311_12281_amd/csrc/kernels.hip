@@ -18,14 +18,16 @@
 // own), compared with the integer threshold closed_needed(p, q, a, b).
 //
 // Edges are processed in degree buckets of the smaller side d_s:
-//   d_s <= 64 : a group of G in {4, 8, 16, 32, 64} lanes per edge, one lane
-//               per element of the smaller list, each binary-searching the
-//               larger list; the group's count is a ballot popcount.
-//   d_s  > 64 : one wave per edge; the smaller list in tiles of 64, each lane
-//               binary-searching the unread remainder of the larger list; the
-//               remainder shrinks tile by tile because both lists are sorted.
-//               The loop stops as soon as the verdict is known (count reached
-//               or unreachable), except when exact counts are requested.
+//   d_s <= 64 : k_group - lanes classify 64 edges at once, then groups of
+//               G in {4, 8, 16, 32, 64} lanes intersect the edges that need
+//               it, one lane per element of the smaller list binary-searching
+//               the larger list; the group's count is a ballot popcount.
+//   d_s  > 64 : k_hub - edges grouped by their larger side v, whose
+//               neighbours are staged in an LDS hash table that the smaller
+//               lists are streamed through (strategy 1 uses k_group with G = 64
+//               instead).
+// Every intersection stops as soon as the verdict is known (count reached or
+// unreachable), except when exact counts are requested.
 #include "scan_internal.h"
 
 #include <climits>
@@ -84,6 +86,13 @@ __device__ __forceinline__ int64_t lower_bound(const int32_t* row, int64_t lo, i
   return lo;
 }
 
+// Position of x's row in A.ci.  In memory this is rp[x]; on the partitioned
+// path A.ci holds the rows of two vertex ranges side by side, and each range
+// is shifted by its own delta.
+__device__ __forceinline__ int64_t row_start(const EdgeArgs& A, int32_t x) {
+  return A.rp[x] - ((x >= A.a_lo && x < A.a_hi) ? A.delta_a : A.delta_b);
+}
+
 // Per-edge decision taken before any intersection.
 struct EdgeView {
   int32_t u, v;       // u = smaller side
@@ -93,26 +102,46 @@ struct EdgeView {
   int32_t core_side;  // ATTACH: endpoint that is the core (u or v)
   int32_t other;      // ATTACH: the non-core endpoint
   int32_t core_label; // ATTACH
+  int32_t mu;         // the edge's graph's mu
   uint8_t work;       // 1: run the intersection
 };
+
+// eps = p/q and mu of the graph holding vertex x (one graph, or a batch of
+// graphs with per-graph parameters looked up through the vertex's graph id).
+__device__ __forceinline__ void graph_params(const EdgeArgs& A, int32_t x, uint64_t& p, uint64_t& q,
+                                             int32_t& mu) {
+  if (A.gid) {
+    const int32_t g = A.gid[x];
+    p = A.gp[g];
+    q = A.gq[g];
+    mu = A.gmu[g];
+  } else {
+    p = A.p;
+    q = A.q;
+    mu = A.mu;
+  }
+}
 
 template <int MODE>
 __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool active, EdgeView& ev,
                                          unsigned long long& n_bound) {
-  ev.work = 0;
+  ev = EdgeView{};
   if (!active) return;
   const int2 uv = A.edges[e];
   ev.u = uv.x;
   ev.v = uv.y;
-  ev.bu = A.rp[ev.u];
-  ev.du = A.rp[ev.u + 1] - ev.bu;
-  ev.bv = A.rp[ev.v];
-  ev.dv = A.rp[ev.v + 1] - ev.bv;
+  ev.du = A.rp[ev.u + 1] - A.rp[ev.u];
+  ev.dv = A.rp[ev.v + 1] - A.rp[ev.v];
+  ev.bu = row_start(A, ev.u);
+  ev.bv = row_start(A, ev.v);
   const uint64_t a = (uint64_t)ev.du + 1, b = (uint64_t)ev.dv + 1;
   if (MODE == MODE_COUNTS) {
+    ev.need = 0;
     ev.work = 1;
     return;
   }
+  uint64_t p, q;
+  graph_params(A, ev.u, p, q, ev.mu);
   if (MODE == MODE_CORES) {
     if (A.pruning) {
       const uint8_t ru = ld_u8(A.role + ev.u), rv = ld_u8(A.role + ev.v);
@@ -137,13 +166,42 @@ __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool acti
     if (A.pruning && ld_i32(A.label + ev.other) <= ev.core_label) return;  // no smaller label possible
   }
   // |N[u] & N[v]| <= min(a, b) = a, so a q^2 < p^2 b already means dissimilar.
-  if (A.pruning && a * A.q * A.q < A.p * A.p * b) {
+  if (A.pruning && a * q * q < p * p * b) {
     ev.work = 3;
     ++n_bound;
     return;
   }
-  ev.need = (int32_t)closed_needed(A.p, A.q, a, b);
+  ev.need = (int32_t)closed_needed(p, q, a, b);
   ev.work = 1;
+}
+
+// Fields of an edge already known to need an intersection (phase B of the
+// LDS-hash kernel).  Returns false for a cores-pass edge whose two roles have
+// become known in the meantime: it is deferred like any other such edge.
+template <int MODE>
+__device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, EdgeView& ev) {
+  const int2 uv = A.edges[e];
+  ev.u = uv.x;
+  ev.v = uv.y;
+  ev.du = A.rp[ev.u + 1] - A.rp[ev.u];
+  ev.dv = A.rp[ev.v + 1] - A.rp[ev.v];
+  ev.bu = row_start(A, ev.u);
+  ev.bv = row_start(A, ev.v);
+  ev.need = 0;
+  ev.work = 1;
+  if (MODE == MODE_COUNTS) return true;
+  uint64_t p, q;
+  graph_params(A, ev.u, p, q, ev.mu);
+  ev.need = (int32_t)closed_needed(p, q, (uint64_t)ev.du + 1, (uint64_t)ev.dv + 1);
+  if (MODE == MODE_CORES) {
+    if (A.pruning && ld_u8(A.role + ev.u) != ROLE_UNK && ld_u8(A.role + ev.v) != ROLE_UNK) return false;
+  } else if (MODE == MODE_ATTACH) {
+    const bool cu = ld_u8(A.role + ev.u) == ROLE_CORE;
+    ev.core_side = cu ? ev.u : ev.v;
+    ev.other = cu ? ev.v : ev.u;
+    ev.core_label = A.label[ev.core_side];
+  }
+  return true;
 }
 
 // Effect of a decided edge; executed by one lane.
@@ -151,20 +209,23 @@ template <int MODE>
 __device__ __forceinline__ void apply(const EdgeArgs& A, int64_t e, const EdgeView& ev, bool sim,
                                       int32_t closed) {
   if (MODE == MODE_COUNTS) {
-    const int64_t pu = lower_bound(A.ci, ev.bu, ev.bu + ev.du, ev.v);
-    const int64_t pv = lower_bound(A.ci, ev.bv, ev.bv + ev.dv, ev.u);
-    if (pu < ev.bu + ev.du && A.ci[pu] == ev.v) A.counts[pu] = closed;
-    if (pv < ev.bv + ev.dv && A.ci[pv] == ev.u) A.counts[pv] = closed;
+    if (A.edge_counts) A.edge_counts[e] = closed;
+    if (A.counts) {
+      const int64_t pu = lower_bound(A.ci, ev.bu, ev.bu + ev.du, ev.v);
+      const int64_t pv = lower_bound(A.ci, ev.bv, ev.bv + ev.dv, ev.u);
+      if (pu < ev.bu + ev.du && A.ci[pu] == ev.v) A.counts[pu] = closed;
+      if (pv < ev.bv + ev.dv && A.ci[pv] == ev.u) A.counts[pv] = closed;
+    }
     return;
   }
   if (MODE == MODE_CORES) {
     A.state[e] = sim ? SIM_YES : SIM_NO;
     if (sim) {
-      if (atomicAdd(A.lower + ev.u, 1) + 1 >= A.mu) st_u8(A.role + ev.u, ROLE_CORE);
-      if (atomicAdd(A.lower + ev.v, 1) + 1 >= A.mu) st_u8(A.role + ev.v, ROLE_CORE);
+      if (atomicAdd(A.lower + ev.u, 1) + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
+      if (atomicAdd(A.lower + ev.v, 1) + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
     } else {
-      if (atomicSub(A.upper + ev.u, 1) - 1 < A.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
-      if (atomicSub(A.upper + ev.v, 1) - 1 < A.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
+      if (atomicSub(A.upper + ev.u, 1) - 1 < ev.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
+      if (atomicSub(A.upper + ev.v, 1) - 1 < ev.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
     }
   } else if (MODE == MODE_MERGE) {
     A.state[e] = sim ? SIM_YES : SIM_NO;
@@ -195,109 +256,402 @@ __device__ __forceinline__ void flush_stats(const EdgeArgs& A, int mode, unsigne
   }
 }
 
-// Buckets 0-4: G lanes per edge, d_s <= G.
+// A group of G lanes intersects the smaller list nbr(u) (length du) with the
+// larger list nbr(v) (length dv): nbr(u) in tiles of G elements, every lane
+// binary-searching its element in the unread remainder of nbr(v) (both lists
+// are sorted, so the remainder only shrinks).  cnt receives the open common
+// neighbours found, consumed the elements of nbr(u) read.  Unless `exact`,
+// the loop stops as soon as the verdict against need_open is certain.
+// Returns 2 (similar), 3 (dissimilar) or 1 (full count, undecided).
+template <int G>
+__device__ __forceinline__ int group_intersect(const int32_t* Arow, int64_t du, const int32_t* B,
+                                               int64_t dv, int32_t need_open, bool exact, int sub,
+                                               int gbase, uint64_t gmask, int32_t& cnt,
+                                               int64_t& consumed) {
+  cnt = 0;
+  consumed = 0;
+  int64_t lo = 0;
+  for (int64_t t = 0; t < du; t += G) {
+    const int64_t i = t + sub;
+    int64_t pos = dv;
+    bool f = false;
+    if (i < du) {
+      const int32_t x = Arow[i];
+      pos = lower_bound(B, lo, dv, x);
+      f = pos < dv && B[pos] == x;
+    }
+    cnt += __popcll(__ballot(f) & gmask);
+    const int64_t take = du - t < G ? du - t : G;
+    consumed += take;
+    lo = __shfl(pos, gbase + (int)(take - 1), 64);
+    if (!exact) {
+      if (cnt >= need_open) return 2;
+      int64_t rem = du - (t + take);
+      if (dv - lo < rem) rem = dv - lo;
+      if (cnt + rem < need_open) return 3;
+    }
+    if (lo >= dv) break;  // the larger list is exhausted
+  }
+  return 1;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_t(T x, int src) {
+  return __shfl(x, src, 64);
+}
+
+// Every lane classifies one edge of a chunk of 64 and applies the edges that
+// need no intersection; the edges that do are then taken 64/G at a time, one
+// per group of G lanes (the edge's fields are broadcast from the lane that
+// classified it).  Buckets 0-4 use G >= d_s (one tile); G = 64 also serves the
+// last bucket when it runs without the LDS-hash kernel.
 template <int MODE, int G>
-__global__ __launch_bounds__(kBlock) void k_edges_group(EdgeArgs A) {
-  constexpr int kPerWave = 64 / G;
+__global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
+  constexpr int kGroups = 64 / G;
   const int lane = threadIdx.x & 63;
-  const int sub = lane & (G - 1);
-  const int gbase = lane & ~(G - 1);
+  const int grp = lane / G, sub = lane & (G - 1), gbase = lane & ~(G - 1);
   const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+  const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
-  for (int64_t t = A.e_begin + wave * kPerWave; t < A.e_end; t += nwaves * kPerWave) {
-    const int64_t e = t + lane / G;
+  for (int64_t base = A.e_begin + wave * 64; base < A.e_end; base += nwaves * 64) {
+    const int64_t e = base + lane;
     EdgeView ev;
     unsigned long long nb = 0;
     classify<MODE>(A, e, e < A.e_end, ev, nb);
-    bool found = false;
-    if (ev.work == 1 && sub < ev.du) {
-      const int32_t x = A.ci[ev.bu + sub];
-      const int64_t pos = lower_bound(A.ci, ev.bv, ev.bv + ev.dv, x);
-      found = pos < ev.bv + ev.dv && A.ci[pos] == x;
-    }
-    const int32_t cnt = __popcll(__ballot(found) & gmask);
-    if (sub == 0) {
-      n_bound += nb;
-      if (ev.work == 1) {
+    n_bound += nb;
+    bool surv = false;
+    if (ev.work == 2) {
+      apply<MODE>(A, e, ev, true, 0);
+    } else if (ev.work == 3) {
+      if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev, false, 0);
+    } else if (ev.work == 1) {
+      if (!exact && ev.need - 2 <= 0) {
         ++n_eval;
-        n_probe += (unsigned long long)ev.du;
-        const int32_t closed = cnt + 2;
-        apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : closed >= ev.need, closed);
-      } else if (ev.work == 2) {
         apply<MODE>(A, e, ev, true, 0);
-      } else if (ev.work == 3 && MODE != MODE_ATTACH) {
-        apply<MODE>(A, e, ev, false, 0);
+      } else {
+        surv = true;
       }
     }
-  }
-  flush_stats(A, MODE, n_eval, n_bound, n_probe);
-}
-
-// Bucket 5: one wave per edge, d_s > 64.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_wave(EdgeArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
-  const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
-  unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
-  for (int64_t e = A.e_begin + wave; e < A.e_end; e += nwaves) {
-    EdgeView ev;
-    unsigned long long nb = 0;
-    classify<MODE>(A, e, true, ev, nb);
-    n_bound += (lane == 0) ? nb : 0;
-    if (ev.work == 2 || ev.work == 3) {
-      if (lane == 0 && (ev.work == 2 || MODE != MODE_ATTACH)) apply<MODE>(A, e, ev, ev.work == 2, 0);
-      continue;
-    }
-    if (ev.work != 1) continue;
-    const int32_t* B = A.ci + ev.bv;
-    const int32_t* Arow = A.ci + ev.bu;
-    const int32_t need_open = ev.need - 2;
-    int32_t cnt = 0;
-    int64_t lo = 0, consumed = 0;
-    bool decided = false, sim = false;
-    if (!exact && need_open <= 0) { decided = true; sim = true; }
-    for (int64_t t = 0; t < ev.du && !decided; t += 64) {
-      const int64_t i = t + lane;
-      const bool valid = i < ev.du;
-      int64_t pos = ev.dv;
-      bool f = false;
-      if (valid) {
-        const int32_t x = Arow[i];
-        pos = lower_bound(B, lo, ev.dv, x);
-        f = pos < ev.dv && B[pos] == x;
-      }
-      cnt += __popcll(__ballot(f));
-      const int64_t take = ev.du - t < 64 ? ev.du - t : 64;
-      consumed += take;
-      lo = __shfl(pos, (int)(take - 1), 64);
-      if (!exact) {
-        if (cnt >= need_open) { decided = true; sim = true; }
-        else {
-          int64_t rem = ev.du - (t + take);
-          if (ev.dv - lo < rem) rem = ev.dv - lo;
-          if (cnt + rem < need_open) { decided = true; sim = false; }
+    uint64_t pending = __ballot(surv);
+    while (pending) {
+      uint64_t mk = pending;
+      for (int j = 0; j < grp; ++j) mk &= mk - 1;
+      const bool act = mk != 0;
+      const int src = act ? __ffsll((unsigned long long)mk) - 1 : lane;
+      EdgeView w;
+      w.u = shfl_t(ev.u, src);
+      w.v = shfl_t(ev.v, src);
+      w.bu = shfl_t(ev.bu, src);
+      w.bv = shfl_t(ev.bv, src);
+      w.du = shfl_t(ev.du, src);
+      w.dv = shfl_t(ev.dv, src);
+      w.need = shfl_t(ev.need, src);
+      w.core_side = shfl_t(ev.core_side, src);
+      w.other = shfl_t(ev.other, src);
+      w.core_label = shfl_t(ev.core_label, src);
+      w.mu = shfl_t(ev.mu, src);
+      const int64_t we = shfl_t(e, src);
+      if (act) {
+        int32_t cnt;
+        int64_t consumed;
+        const int verdict = group_intersect<G>(A.ci + w.bu, w.du, A.ci + w.bv, w.dv, w.need - 2, exact,
+                                               sub, gbase, gmask, cnt, consumed);
+        if (sub == 0) {
+          ++n_eval;
+          n_probe += (unsigned long long)consumed;
+          const bool sim = verdict == 2 ? true : verdict == 3 ? false : (cnt + 2 >= w.need);
+          apply<MODE>(A, we, w, MODE == MODE_COUNTS ? false : sim, cnt + 2);
         }
       }
-      if (lo >= ev.dv && !decided) break;  // larger list exhausted
-    }
-    if (!decided) sim = (cnt + 2) >= ev.need;
-    if (lane == 0) {
-      ++n_eval;
-      n_probe += (unsigned long long)consumed;
-      apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : sim, cnt + 2);
+      for (int j = 0; j < kGroups && pending; ++j) pending &= pending - 1;
     }
   }
   flush_stats(A, MODE, n_eval, n_bound, n_probe);
 }
 
-__global__ void k_init(int32_t n, const int64_t* rp, int32_t mu, int32_t* lower, int32_t* upper,
-                       uint8_t* role, int32_t* parent) {
+// Last bucket (d_u > 64), grouped by the larger side v.  A job is up to
+// kHubJobEdges consecutive in-edges (u_i, v) of one v; blocks take jobs from a
+// device counter, heaviest v first.
+//   Phase A: every thread classifies in-edges; those needing an intersection
+//            are appended to the job's slice of the worklist.
+//   Phase B: the survivors are processed kHubBatch at a time.  For each batch
+//            the block fills an LDS hash table with nbr(v) (multiplicative
+//            hash, linear probing, at most half full) and every wave streams
+//            the smaller lists nbr(u_i) of its survivors through it, 64 probes
+//            per step, counting hits with a ballot.  Rows longer than the
+//            table are taken in windows of kHubWindow consecutive elements of
+//            nbr(v); a window holds the values below the first element of the
+//            next one, and each survivor keeps its read position and next
+//            element in LDS, so nbr(u_i) is read once in total and windows
+//            below every survivor's next element are not built at all.  A
+//            survivor stops as soon as its verdict is certain.
+// Bucketed open addressing: kHubSlots int32 slots viewed as buckets of 4;
+// an element goes to the first free slot of bucket hash(x), or of the next
+// buckets in turn if that one is full.  Slots fill in order within a bucket,
+// so a bucket with a free last slot has never overflowed: a probe reads one
+// bucket (a single 16-byte LDS load) and continues only when it is full.
+constexpr int kHubBuckets = kHubSlots / 4;
+__device__ __forceinline__ uint32_t hub_hash(int32_t x) {
+  return ((uint32_t)x * 0x9E3779B1u) >> (32 - (kHubLog2Slots - 2));
+}
+
+__device__ __forceinline__ void hub_insert(int32_t* table, int32_t x) {
+  uint32_t b = hub_hash(x);
+  while (true) {
+    int32_t* slot = table + 4 * b;
+    if (atomicCAS(slot + 0, -1, x) == -1) return;
+    if (atomicCAS(slot + 1, -1, x) == -1) return;
+    if (atomicCAS(slot + 2, -1, x) == -1) return;
+    if (atomicCAS(slot + 3, -1, x) == -1) return;
+    b = (b + 1) & (kHubBuckets - 1);
+  }
+}
+
+__device__ __forceinline__ bool bucket_has(int4 q, int32_t x) {
+  return q.x == x || q.y == x || q.z == x || q.w == x;
+}
+
+// Rest of a probe whose first bucket was full.
+__device__ __noinline__ bool hub_probe_tail(const int4* T, int32_t x) {
+  uint32_t b = (hub_hash(x) + 1) & (kHubBuckets - 1);
+  while (true) {
+    const int4 q = T[b];
+    if (bucket_has(q, x)) return true;
+    if (q.w == -1) return false;
+    b = (b + 1) & (kHubBuckets - 1);
+  }
+}
+
+// Exclusive prefix sum of one int32 per thread over a block of kHubBlock
+// threads; returns the sum of all values through *total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t x, int32_t* wsum, int32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t incl = x;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+  for (int w = 0; w < kHubBlock / 64; ++w) {
+    const int32_t t = wsum[w];
+    off += (w < wave) ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  return off + incl - x;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs,
+                                                   unsigned long long* counter, int32_t* wl) {
+  constexpr int kGroups = kHubBlock / kHubGroup;
+  constexpr int kStep = kHubGroup * kHubUnroll;  // elements per group step
+  __shared__ __align__(16) int32_t table[kHubSlots];
+  __shared__ int64_t q_bu[kHubBatch];
+  __shared__ unsigned long long q_acc[kHubBatch];  // (consumed in this window) << 32 | hits
+  __shared__ int32_t q_du[kHubBatch];
+  __shared__ int32_t q_need[kHubBatch];   // open common neighbours needed
+  __shared__ int32_t q_cnt[kHubBatch];    // open common neighbours found before this window
+  __shared__ int32_t q_pos[kHubBatch];    // elements of nbr(u) consumed before this window
+  __shared__ int32_t q_end[kHubBatch];    // end of this window's part of nbr(u)
+  __shared__ int32_t q_next[kHubBatch];   // next unread element of nbr(u) (INT_MAX at the end)
+  __shared__ int32_t q_choff[kHubBatch + 1];  // first chunk of each survivor in this window
+  __shared__ uint8_t q_st[kHubBatch];     // 0 skipped, 1 active, 2 similar, 3 dissimilar
+  __shared__ int32_t wsum[kHubBlock / 64];
+  __shared__ int64_t s_job;
+  __shared__ int32_t s_n, s_min, s_chunk;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int sub = lane & (kHubGroup - 1), gbase = lane & ~(kHubGroup - 1);
+  const uint64_t gmask = ((1ull << kHubGroup) - 1ull) << gbase;
+  const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
+  const int4* T4 = reinterpret_cast<const int4*>(table);
+  unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
+  while (true) {
+    if (tid == 0) {
+      s_job = (int64_t)atomicAdd(counter, 1ull);
+      s_n = 0;
+    }
+    __syncthreads();
+    const int64_t job = s_job;
+    if (job >= njobs) break;
+    const HubJob J = jobs[job];
+    const int64_t region = J.begin - A.e_begin;
+    // Phase A
+    for (int32_t base = 0; base < J.count; base += kHubBlock) {
+      const int32_t off = base + tid;
+      const int64_t e = J.begin + off;
+      EdgeView ev;
+      unsigned long long nb = 0;
+      classify<MODE>(A, e, off < J.count, ev, nb);
+      n_bound += nb;
+      if (ev.work == 2) {
+        apply<MODE>(A, e, ev, true, 0);
+      } else if (ev.work == 3) {
+        if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev, false, 0);
+      } else if (ev.work == 1) {
+        if (!exact && ev.need - 2 <= 0) {
+          ++n_eval;
+          apply<MODE>(A, e, ev, true, 0);
+        } else {
+          wl[region + atomicAdd(&s_n, 1)] = off;
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t S = s_n;
+    const int64_t bv = A.rp[J.v];
+    const int64_t dv = A.rp[J.v + 1] - bv;
+    // Phase B
+    for (int32_t b0 = 0; b0 < S; b0 += kHubBatch) {
+      const int32_t nbatch = (S - b0 < kHubBatch) ? S - b0 : kHubBatch;
+      EdgeView ev;
+      int64_t e = 0;
+      if (tid < nbatch) {
+        e = J.begin + wl[region + b0 + tid];
+        const bool keep = load_survivor<MODE>(A, e, ev);
+        q_bu[tid] = ev.bu;
+        q_du[tid] = (int32_t)ev.du;
+        q_need[tid] = ev.need - 2;
+        q_cnt[tid] = 0;
+        q_pos[tid] = 0;
+        q_next[tid] = (keep && ev.du > 0) ? A.ci[ev.bu] : INT_MAX;
+        q_st[tid] = keep ? 1 : 0;
+      }
+      for (int64_t w0 = 0; w0 < dv; w0 += kHubWindow) {
+        const int64_t w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+        const int32_t hi = (w1 < dv) ? A.ci[bv + w1] : INT_MAX;
+        if (tid == 0) {
+          s_min = INT_MAX;
+          s_chunk = 0;
+        }
+        __syncthreads();
+        if (tid < nbatch && q_st[tid] == 1) atomicMin(&s_min, q_next[tid]);
+        __syncthreads();
+        const int32_t mn = s_min;
+        __syncthreads();           // s_min is reset at the top of the next window
+        if (mn == INT_MAX) break;  // every survivor decided or fully read
+        if (mn >= hi) continue;    // no survivor has an element in this window
+        for (int k = tid; k < kHubSlots; k += kHubBlock) table[k] = -1;
+        // this window's part of every active survivor, cut into chunks of kHubChunk
+        int32_t nch = 0;
+        if (tid < nbatch) {
+          q_acc[tid] = 0;
+          if (q_st[tid] == 1 && q_next[tid] < hi) {
+            const int32_t* Arow = A.ci + q_bu[tid];
+            int32_t lo = q_pos[tid], hi2 = q_du[tid];
+            if (hi != INT_MAX) {
+              while (lo < hi2) {
+                const int32_t mid = (lo + hi2) >> 1;
+                if (Arow[mid] < hi) lo = mid + 1;
+                else hi2 = mid;
+              }
+              q_end[tid] = lo;
+            } else {
+              q_end[tid] = hi2;
+            }
+            nch = (q_end[tid] - q_pos[tid] + kHubChunk - 1) / kHubChunk;
+          }
+        }
+        int32_t nchunks;
+        const int32_t choff = block_exclusive_scan(nch, wsum, &nchunks);
+        if (tid < nbatch) q_choff[tid] = choff;
+        if (tid == 0) q_choff[nbatch] = nchunks;
+        __syncthreads();
+        for (int64_t k = w0 + tid; k < w1; k += kHubBlock) hub_insert(table, A.ci[bv + k]);
+        __syncthreads();
+        // groups of kHubGroup lanes take chunks until none are left
+        while (true) {
+          int32_t c = 0;
+          if (sub == 0) c = atomicAdd(&s_chunk, 1);
+          c = __shfl(c, gbase, 64);
+          if (c >= nchunks) break;
+          int32_t lo = 0, hi2 = nbatch;  // survivor k: q_choff[k] <= c < q_choff[k + 1]
+          while (hi2 - lo > 1) {
+            const int32_t mid = (lo + hi2) >> 1;
+            if (q_choff[mid] <= c) lo = mid;
+            else hi2 = mid;
+          }
+          const int k = lo;
+          if (q_st[k] != 1) continue;  // decided by another chunk
+          const int32_t* Arow = A.ci + q_bu[k];
+          const int32_t cs = q_pos[k] + (c - q_choff[k]) * kHubChunk;
+          const int32_t ce = (q_end[k] - cs < kHubChunk) ? q_end[k] : cs + kHubChunk;
+          int32_t hits = 0;
+          for (int32_t p = cs; p < ce; p += kStep) {
+            int32_t x[kHubUnroll];
+            int4 q[kHubUnroll];
+#pragma unroll
+            for (int j = 0; j < kHubUnroll; ++j) {
+              const int32_t i = p + j * kHubGroup + sub;
+              x[j] = (i < ce) ? Arow[i] : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < kHubUnroll; ++j) q[j] = (x[j] >= 0) ? T4[hub_hash(x[j])] : make_int4(0, 0, 0, -1);
+#pragma unroll
+            for (int j = 0; j < kHubUnroll; ++j) {
+              bool f = x[j] >= 0 && bucket_has(q[j], x[j]);
+              if (x[j] >= 0 && !f && q[j].w != -1) f = hub_probe_tail(T4, x[j]);
+              hits += __popcll(__ballot(f) & gmask);
+            }
+          }
+          if (sub == 0) {
+            const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
+            const unsigned long long now = atomicAdd(&q_acc[k], add) + add;
+            if (!exact) {
+              const int32_t cnt = q_cnt[k] + (int32_t)(now & 0xffffffffu);
+              const int32_t done = q_pos[k] + (int32_t)(now >> 32);
+              if (cnt >= q_need[k]) q_st[k] = 2;
+              else if (cnt + (q_du[k] - done) < q_need[k]) q_st[k] = 3;
+            }
+          }
+        }
+        __syncthreads();
+        if (tid < nbatch && q_st[tid] != 0 && q_next[tid] < hi) {
+          // window finished for this survivor (or it was decided on the way)
+          const unsigned long long a = q_acc[tid];
+          const int32_t cnt = q_cnt[tid] + (int32_t)(a & 0xffffffffu);
+          const int32_t pos = q_pos[tid] + (int32_t)(a >> 32);
+          q_cnt[tid] = cnt;
+          q_pos[tid] = pos;
+          if (q_st[tid] == 1) {
+            q_next[tid] = (pos < q_du[tid]) ? A.ci[q_bu[tid] + pos] : INT_MAX;
+            if (!exact) {
+              if (cnt >= q_need[tid]) q_st[tid] = 2;
+              else if (cnt + (q_du[tid] - pos) < q_need[tid]) q_st[tid] = 3;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      __syncthreads();
+      if (tid < nbatch && q_st[tid] != 0) {
+        const int32_t st = q_st[tid], cnt = q_cnt[tid];
+        ++n_eval;
+        n_probe += (unsigned long long)q_pos[tid];
+        const bool sim = st == 2 ? true : st == 3 ? false : (cnt + 2 >= ev.need);
+        apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : sim, cnt + 2);
+      }
+      __syncthreads();
+    }
+    __syncthreads();  // every thread is done with this job's shared values
+  }
+  flush_stats(A, MODE, n_eval, n_bound, n_probe);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_init(int32_t n, const int64_t* rp, int32_t mu, const int32_t* gid, const int32_t* gmu,
+                       int32_t* lower, int32_t* upper, uint8_t* role, int32_t* parent) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
+  if (gid) mu = gmu[gid[u]];
   const int64_t d = rp[u + 1] - rp[u];
   lower[u] = 1;                       // u itself is in N_eps[u]
   upper[u] = (int32_t)(d + 1);        // |N[u]|
@@ -317,9 +671,11 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   }
 }
 
-__global__ void k_finalize(int32_t n, int32_t mu, const int32_t* lower, uint8_t* role) {
+__global__ void k_finalize(int32_t n, int32_t mu, const int32_t* gid, const int32_t* gmu, const int32_t* lower,
+                           uint8_t* role) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
+  if (gid) mu = gmu[gid[u]];
   // A role still unknown here had every incident edge evaluated (an edge is
   // only deferred when both roles are known), so lower is |N_eps[u]| exactly.
   if (role[u] == ROLE_UNK) role[u] = lower[u] >= mu ? ROLE_CORE : ROLE_NONCORE;
@@ -342,11 +698,11 @@ __global__ void k_flatten(int32_t n, const uint8_t* role, int32_t* parent, int32
   label[u] = role[u] == ROLE_CORE ? uf_find(parent, (int32_t)u) : INT_MAX;
 }
 
-__global__ void k_output(int32_t n, const uint8_t* role, const int32_t* label, int32_t* out_labels,
-                         uint8_t* out_roles) {
+__global__ void k_output(int32_t n, const uint8_t* role, const int32_t* label, const int32_t* gid,
+                         const int32_t* gbase, int32_t* out_labels, uint8_t* out_roles) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
-  const int32_t l = label[u];
+  const int32_t l = label[u] - ((gid && label[u] != INT_MAX) ? gbase[gid[u]] : 0);  // batch: local ids
   if (role[u] == ROLE_CORE) {
     out_roles[u] = 1;
     out_labels[u] = l;
@@ -356,6 +712,57 @@ __global__ void k_output(int32_t n, const uint8_t* role, const int32_t* label, i
   } else {
     out_roles[u] = 0;
     out_labels[u] = -1;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Re-thresholding from cached closed counts (serving).  With c_e known for
+// every edge, a query (eps, mu) needs no intersection: each edge is tested
+// with (c q)^2 >= p^2 a b directly (c <= min(a, b) and q max(a, b) < 2^32 keep
+// both sides below 2^64), cores come from exact counts, then the same hook /
+// flatten / attach steps as the full run.
+__global__ void k_rt_init(int32_t n, int32_t* lower, int32_t* parent) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  lower[u] = 1;
+  parent[u] = (int32_t)u;
+}
+
+__global__ void k_rt_edges(int64_t m, const int2* edges, const int64_t* rp, const int32_t* ecount,
+                           uint64_t p, uint64_t q, uint8_t* state, int32_t* lower) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < m; e += stride) {
+    const int2 uv = edges[e];
+    const uint64_t a = (uint64_t)(rp[uv.x + 1] - rp[uv.x]) + 1;
+    const uint64_t b = (uint64_t)(rp[uv.y + 1] - rp[uv.y]) + 1;
+    const uint64_t cq = (uint64_t)ecount[e] * q;
+    const bool sim = cq * cq >= (p * p) * (a * b);
+    state[e] = sim ? SIM_YES : SIM_NO;
+    if (sim) {
+      atomicAdd(lower + uv.x, 1);
+      atomicAdd(lower + uv.y, 1);
+    }
+  }
+}
+
+__global__ void k_rt_roles(int32_t n, int32_t mu, const int32_t* lower, uint8_t* role) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) role[u] = lower[u] >= mu ? ROLE_CORE : ROLE_NONCORE;
+}
+
+__global__ void k_rt_attach(int64_t m, const int2* edges, const uint8_t* state, const uint8_t* role,
+                            int32_t* label) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < m; e += stride) {
+    if (state[e] != SIM_YES) continue;
+    const int2 uv = edges[e];
+    const bool cu = role[uv.x] == ROLE_CORE, cv = role[uv.y] == ROLE_CORE;
+    if (cu == cv) continue;
+    if (cu) atomicMin(label + uv.y, label[uv.x]);
+    else atomicMin(label + uv.x, label[uv.y]);
   }
 }
 
@@ -370,26 +777,48 @@ template <int MODE>
 void launch_edges_mode(hipStream_t s, int bucket, const EdgeArgs& a) {
   const int64_t m = a.e_end - a.e_begin;
   if (m <= 0) return;
-  constexpr int64_t kCap = 16384;
+  const unsigned grid = blocks_for(m, kBlock, 8192);
   switch (bucket) {
-    case 0: k_edges_group<MODE, 4><<<blocks_for(m, 64, kCap), kBlock, 0, s>>>(a); break;
-    case 1: k_edges_group<MODE, 8><<<blocks_for(m, 32, kCap), kBlock, 0, s>>>(a); break;
-    case 2: k_edges_group<MODE, 16><<<blocks_for(m, 16, kCap), kBlock, 0, s>>>(a); break;
-    case 3: k_edges_group<MODE, 32><<<blocks_for(m, 8, kCap), kBlock, 0, s>>>(a); break;
-    case 4: k_edges_group<MODE, 64><<<blocks_for(m, 4, kCap), kBlock, 0, s>>>(a); break;
-    default: k_edges_wave<MODE><<<blocks_for(m, 4, kCap), kBlock, 0, s>>>(a); break;
+    case 0: k_group<MODE, 4><<<grid, kBlock, 0, s>>>(a); break;
+    case 1: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
+    case 2: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
+    case 3: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
+    default: k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a); break;
   }
 }
 
 }  // namespace
 
 void launch_init(hipStream_t s, int32_t n, const int64_t* rp, int32_t mu, int32_t* lower,
-                 int32_t* upper, uint8_t* role, int32_t* parent) {
-  if (n > 0) k_init<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, rp, mu, lower, upper, role, parent);
+                 int32_t* upper, uint8_t* role, int32_t* parent, const int32_t* gid, const int32_t* gmu) {
+  if (n > 0) k_init<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, rp, mu, gid, gmu, lower, upper, role, parent);
 }
 
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
   if (n > 0) k_fill_u8<<<blocks_for(n, 256 * 16, 8192), 256, 0, s>>>(p, n, v);
+}
+
+template <int MODE>
+void launch_edges_width(hipStream_t s, int lanes, const EdgeArgs& a) {
+  const int64_t m = a.e_end - a.e_begin;
+  if (m <= 0) return;
+  const unsigned grid = blocks_for(m, kBlock, 8192);
+  switch (lanes) {
+    case 4: k_group<MODE, 4><<<grid, kBlock, 0, s>>>(a); break;
+    case 8: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
+    case 16: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
+    case 32: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
+    default: k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a); break;
+  }
+}
+
+void launch_edges_lanes(hipStream_t s, int mode, int lanes, const EdgeArgs& a) {
+  switch (mode) {
+    case MODE_CORES: launch_edges_width<MODE_CORES>(s, lanes, a); break;
+    case MODE_MERGE: launch_edges_width<MODE_MERGE>(s, lanes, a); break;
+    case MODE_ATTACH: launch_edges_width<MODE_ATTACH>(s, lanes, a); break;
+    default: launch_edges_width<MODE_COUNTS>(s, lanes, a); break;
+  }
 }
 
 void launch_edges(hipStream_t s, int mode, int bucket, const EdgeArgs& a) {
@@ -401,8 +830,25 @@ void launch_edges(hipStream_t s, int mode, int bucket, const EdgeArgs& a) {
   }
 }
 
-void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role) {
-  if (n > 0) k_finalize<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, lower, role);
+void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
+                unsigned long long* counter, int32_t* worklist) {
+  if (njobs <= 0) return;
+  const unsigned grid = blocks_for(njobs, 1, 1024);
+  switch (mode) {
+    case MODE_CORES: k_hub<MODE_CORES><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
+    case MODE_MERGE: k_hub<MODE_MERGE><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
+    case MODE_ATTACH: k_hub<MODE_ATTACH><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
+    default: k_hub<MODE_COUNTS><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
+  }
+}
+
+void launch_zero_u64(hipStream_t s, unsigned long long* p, int n) {
+  if (n > 0) k_zero_u64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+}
+
+void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,
+                           const int32_t* gid, const int32_t* gmu) {
+  if (n > 0) k_finalize<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, gid, gmu, lower, role);
 }
 
 void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,
@@ -415,8 +861,23 @@ void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* pare
 }
 
 void launch_output(hipStream_t s, int32_t n, const uint8_t* role, const int32_t* label,
-                   int32_t* out_labels, uint8_t* out_roles) {
-  if (n > 0) k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, out_labels, out_roles);
+                   int32_t* out_labels, uint8_t* out_roles, const int32_t* gid, const int32_t* gbase) {
+  if (n > 0) k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, gid, gbase, out_labels, out_roles);
+}
+
+
+void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
+                        const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
+                        uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
+                        int32_t* out_labels, uint8_t* out_roles) {
+  if (n <= 0) return;
+  k_rt_init<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, lower, parent);
+  if (m > 0) k_rt_edges<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, rp, ecount, p, q, state, lower);
+  k_rt_roles<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, lower, role);
+  if (m > 0) k_hook<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, state, role, parent);
+  k_flatten<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, parent, label);
+  if (m > 0) k_rt_attach<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, state, role, label);
+  k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, nullptr, nullptr, out_labels, out_roles);
 }
 
 }  // namespace scan

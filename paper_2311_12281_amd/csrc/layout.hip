@@ -6,6 +6,10 @@
 // partition: per-block bucket counts, one exclusive scan, ordered scatter.
 #include "scan_internal.h"
 
+#include <algorithm>
+#include <thread>
+#include <vector>
+
 namespace scan {
 namespace {
 
@@ -72,13 +76,24 @@ __global__ void k_check_arcs(int32_t n, int64_t nnz, const int64_t* rp, const in
   if (e) atomicOr(err, e);
 }
 
-// Bucket of the arc i if it is the owner arc of its edge (its row is the
-// smaller side by (degree, id)), else -1.
+// Owner arc of each undirected edge, and its bucket (or -1 if arc i does not
+// own its edge).  With x = row of arc i and y = its neighbour, the edge's
+// smaller side by (degree, id) is u and the larger is v:
+//   buckets 0-5 (d_u <= 64, or d_v <= kHubMinDegree): owned by the arc in u's
+//     row, so these buckets list their edges grouped by the smaller side;
+//   bucket 6 (d_u > 64 and d_v > kHubMinDegree): owned by the arc in v's row,
+//     so the bucket lists its edges grouped by the larger side - each job of
+//     the LDS-hash kernel stages one larger list and streams the smaller
+//     lists of its in-edges.
 __device__ inline int arc_bucket(const int64_t* rp, const int32_t* ci, const int32_t* src, int64_t i) {
-  const int32_t u = src[i], v = ci[i];
-  const int64_t du = rp[u + 1] - rp[u], dv = rp[v + 1] - rp[v];
-  const bool own = du < dv || (du == dv && u < v);
-  return own ? bucket_of(du) : -1;
+  const int32_t x = src[i], y = ci[i];
+  const int64_t dx = rp[x + 1] - rp[x], dy = rp[y + 1] - rp[y];
+  const bool x_smaller = dx < dy || (dx == dy && x < y);
+  if (x_smaller) {
+    const int b = bucket_of(dx);
+    return (b < 5 || dy <= kHubMinDegree) ? b : -1;
+  }
+  return (dy > 64 && dx > kHubMinDegree) ? 6 : -1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bucket_counts(int64_t nnz, const int64_t* rp,
@@ -123,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(int64_t nnz, const in
     if (b >= 0) {
       int64_t pos = running[b] + myrank;
       for (int w = 0; w < wave; ++w) pos += wave_cnt[b][w];
-      edges[pos] = make_int2(src[i], ci[i]);
+      // stored as (smaller side, larger side)
+      edges[pos] = (b == kNumBuckets - 1) ? make_int2(ci[i], src[i]) : make_int2(src[i], ci[i]);
     }
     __syncthreads();
     if (threadIdx.x < kNumBuckets) {
@@ -189,11 +205,17 @@ hipError_t exclusive_scan(hipStream_t s, const int64_t* in, int64_t* out, int64_
   return e != hipSuccess ? e : f;
 }
 
+
 }  // namespace
 
-hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* d_rp,
-                        const int32_t* d_ci, int validate, int2** d_edges_out, LayoutResult* out) {
+hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
+                        const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
+                        int2** d_edges_out, HubJob** d_jobs_out, LayoutResult* out) {
   hipError_t e = hipSuccess;
+  int64_t* d_hub = nullptr;
+  HubJob* d_jobs = nullptr;
+  *d_jobs_out = nullptr;
+  out->hub_jobs = 0;
   int32_t* d_flags = nullptr;  // [0] = error bits, [1] = max degree
   int32_t* d_src = nullptr;
   int64_t* d_cnt = nullptr;
@@ -245,10 +267,93 @@ hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* d_
                                                         d_cnt + ncnt, d_edges);
   LTRY(hipGetLastError());
   LTRY(hipStreamSynchronize(s));
+  {
+    // Jobs of the last bucket.  Its edges are listed by increasing larger
+    // side v and, within v, in the order of v's row; a job is a run of one v's
+    // in-edges holding at most kHubJobEdges edges and at most kHubJobWork
+    // elements of smaller lists, so that the heaviest tables are shared by
+    // many blocks.  The table is ordered by decreasing deg(v).  Computed on the
+    // host from the caller's CSR with the predicate the device used.
+    const int64_t b6 = out->bucket_off[kNumBuckets - 1], e6 = out->bucket_off[kNumBuckets];
+    if (e6 > b6 && n > 0) {
+      auto deg = [&](int32_t x) { return h_rp[x + 1] - h_rp[x]; };
+      auto in_edge = [&](int32_t v, int32_t u) {  // edge (u, v) is in the last bucket, owned by v
+        const int64_t dv = deg(v), du = deg(u);
+        const bool u_smaller = du < dv || (du == dv && u < v);
+        return u_smaller && du > 64 && dv > kHubMinDegree;
+      };
+      const int nth = 16;
+      std::vector<std::vector<HubJob>> part(nth);
+      std::vector<int64_t> cnt((size_t)n, 0);
+      std::vector<std::thread> th;
+      // pass 1: in-edge counts per v (for the segment starts)
+      for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t]() {
+          for (int32_t v = t; v < n; v += nth) {
+            if (deg(v) <= kHubMinDegree) continue;
+            int64_t c = 0;
+            for (int64_t k = h_rp[v]; k < h_rp[v + 1]; ++k) c += in_edge(v, h_ci[k]);
+            cnt[(size_t)v] = c;
+          }
+        });
+      for (auto& x : th) x.join();
+      th.clear();
+      std::vector<int64_t> start((size_t)n);
+      int64_t acc = 0;
+      for (int32_t v = 0; v < n; ++v) {
+        start[(size_t)v] = acc;
+        acc += cnt[(size_t)v];
+      }
+      if (acc != e6 - b6) {
+        out->error = 32;  // host and device disagree on the bucket (cannot happen for a valid CSR)
+        goto done;
+      }
+      // pass 2: cut each v's in-edges into jobs
+      for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t]() {
+          for (int32_t v = t; v < n; v += nth) {
+            if (cnt[(size_t)v] == 0) continue;
+            HubJob J;
+            J.v = v;
+            J.begin = b6 + start[(size_t)v];
+            J.count = 0;
+            int64_t work = 0;
+            for (int64_t k = h_rp[v]; k < h_rp[v + 1]; ++k) {
+              const int32_t u = h_ci[k];
+              if (!in_edge(v, u)) continue;
+              if (J.count > 0 && (J.count == kHubJobEdges || work + deg(u) > kHubJobWork)) {
+                part[(size_t)t].push_back(J);
+                J.begin += J.count;
+                J.count = 0;
+                work = 0;
+              }
+              ++J.count;
+              work += deg(u);
+            }
+            part[(size_t)t].push_back(J);
+          }
+        });
+      for (auto& x : th) x.join();
+      std::vector<HubJob> jobs;
+      for (auto& p : part) jobs.insert(jobs.end(), p.begin(), p.end());
+      std::stable_sort(jobs.begin(), jobs.end(), [&](const HubJob& a, const HubJob& b) {
+        const int64_t da = deg(a.v), db = deg(b.v);
+        return da != db ? da > db : a.begin < b.begin;
+      });
+      out->hub_jobs = (int64_t)jobs.size();
+      LTRY(hipMalloc((void**)&d_jobs, sizeof(HubJob) * (jobs.empty() ? 1 : jobs.size())));
+      LTRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice, s));
+      LTRY(hipStreamSynchronize(s));
+    }
+  }
   *d_edges_out = d_edges;
   d_edges = nullptr;
+  *d_jobs_out = d_jobs;
+  d_jobs = nullptr;
 done:
   hipStreamSynchronize(s);
+  if (d_hub) hipFree(d_hub);
+  if (d_jobs) hipFree(d_jobs);
   if (d_edges) hipFree(d_edges);
   if (d_cnt) hipFree(d_cnt);
   if (d_src) hipFree(d_src);

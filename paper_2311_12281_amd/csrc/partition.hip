@@ -1,0 +1,395 @@
+// Partition-based path for graphs larger than the device budget (GPUSCAN++
+// Section 5: edge-extended subgraphs, Def. 5.1; exactness of sigma on them,
+// Lemma 5.1; the three streamed passes of Alg. 5).
+//
+// Redesign for one MI355X: instead of packing edges greedily into subgraphs
+// (Alg. 5, host loop), vertices are cut into contiguous ranges ("blocks") whose
+// rows fit half of the device row buffer.  The edges between blocks i <= j are
+// processed with the complete rows of both blocks on the device, so every
+// intersection sees both full neighbourhoods - the edge-extended subgraph of
+// those edges - and sigma is exact (Lemma 5.1).  Per-vertex state (bounds,
+// roles, parents, labels) and row_ptr stay resident for the whole run; edge
+// states travel with their edges (uploaded before, read back after each chunk,
+// like the store step of Alg. 5).  One run streams the pairs three times: the
+// cores pass, the merge pass (known-similar hooks, then progressive merging,
+// chunk by chunk) and the attach pass; union-find roots and labels are global,
+// so unions made in one chunk are seen by all later ones (no per-subgraph
+// re-initialisation of the forest).
+#include "graph.h"
+
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace scan {
+
+uint64_t inmemory_footprint(int32_t n, int64_t nnz) {
+  const uint64_t m = (uint64_t)nnz / 2;
+  // row_ptr, col_idx, oriented edges, hub worklist, edge state, per-vertex state + outputs
+  return 8ull * ((uint64_t)n + 1) + 4ull * nnz + 8ull * m + 4ull * m + 1ull * m + 22ull * n + (1ull << 20);
+}
+
+namespace {
+
+constexpr uint64_t kEdgeBytes = 8 + 1 + 4;  // streamed per edge: endpoints, state, count
+
+int bucket_small(int64_t ds) {  // the group kernels' buckets (no LDS-hash bucket here)
+  const int b = bucket_of(ds);
+  return b < 5 ? b : 5;
+}
+
+}  // namespace
+
+void part_release(scan_graph* g) {
+  PartPlan& P = g->part;
+  if (P.h_ci) (void)hipHostFree(P.h_ci);
+  if (P.h_edges) (void)hipHostFree(P.h_edges);
+  if (P.h_state) (void)hipHostFree(P.h_state);
+  if (P.h_ecount) (void)hipHostFree(P.h_ecount);
+  void* d[] = {P.d_rows, P.d_edges, P.d_state, P.d_ecount};
+  for (void* p : d)
+    if (p) (void)hipFree(p);
+  P = PartPlan();
+}
+
+// Host-side CSR checks (the graph never resides on the device whole):
+// same conditions as the device validation of the in-memory path.
+int part_validate(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, bool full) {
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v] || rp[v] < 0 || rp[v + 1] > nnz) return fail(SCAN_E_GRAPH, "row offsets not monotone");
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<int> bad((size_t)nth, 0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      for (int32_t u = t; u < n && !bad[(size_t)t]; u += nth)
+        for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+          const int32_t v = ci[k];
+          if (v < 0 || v >= n) { bad[(size_t)t] = 2; break; }
+          if (!full) continue;
+          if (v == u) { bad[(size_t)t] = 4; break; }
+          if (k > rp[u] && ci[k - 1] >= v) { bad[(size_t)t] = 8; break; }
+          if (!std::binary_search(ci + rp[v], ci + rp[v + 1], u)) { bad[(size_t)t] = 16; break; }
+        }
+    });
+  for (auto& x : th) x.join();
+  for (int b : bad)
+    if (b) return fail(SCAN_E_GRAPH, "CSR rejected (flag 0x%x: 2 id range, 4 self-loop, 8 row order/duplicate, "
+                                     "16 missing reverse arc)", b);
+  return SCAN_OK;
+}
+
+int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t budget) {
+  PartPlan& P = g->part;
+  const int32_t n = g->n;
+  const int64_t nnz = g->nnz;
+  const int64_t m = nnz / 2;
+  const uint64_t resident = 8ull * ((uint64_t)n + 1) + 22ull * (uint64_t)n + (1ull << 20);
+  if (budget <= resident + (1ull << 16))
+    return fail(SCAN_E_NOMEM, "budget %llu bytes cannot hold the per-vertex state (%llu bytes)",
+                (unsigned long long)budget, (unsigned long long)resident);
+  const uint64_t rest = budget - resident;
+  int64_t chunk_cap = (int64_t)((rest / 4) / kEdgeBytes);
+  if (chunk_cap > m) chunk_cap = m;
+  if (chunk_cap < 1) chunk_cap = 1;
+  const int64_t row_cap = (int64_t)((rest - (uint64_t)chunk_cap * kEdgeBytes) / 4);  // two blocks
+  const int64_t blk_cap = row_cap / 2;
+  int64_t maxdeg = 0;
+  for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp[v + 1] - rp[v]);
+  if (maxdeg > blk_cap || blk_cap < 1)
+    return fail(SCAN_E_NOMEM, "budget too small: a row of %lld neighbours does not fit a block of %lld",
+                (long long)maxdeg, (long long)blk_cap);
+  // blocks: contiguous vertex ranges with at most blk_cap arcs
+  P.block_lo.clear();
+  P.block_lo.push_back(0);
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t start = rp[P.block_lo.back()];
+    if (rp[v + 1] - start > blk_cap) P.block_lo.push_back(v);
+  }
+  P.block_lo.push_back(n);
+  const int32_t K = (int32_t)P.block_lo.size() - 1;
+  P.h_rp.assign(rp, rp + n + 1);
+  auto block_of = [&](int32_t x) {
+    return (int32_t)(std::upper_bound(P.block_lo.begin(), P.block_lo.end(), x) - P.block_lo.begin()) - 1;
+  };
+  auto pair_index = [&](int32_t i, int32_t j) { return (int64_t)i * K - (int64_t)i * (i - 1) / 2 + (j - i); };
+  const int64_t npairs = (int64_t)K * (K + 1) / 2;
+  const int NB = kNumBuckets - 1 + 1;  // buckets 0..5
+  std::vector<int64_t> cnt((size_t)(npairs * NB), 0);
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  // an edge {u, v} is listed from the row of its endpoint in the lower block
+  // (the smaller id inside one block); it is stored as (smaller, larger) by
+  // (degree, id) and bucketed by the smaller degree
+  auto for_edges_of_block = [&](int32_t i, auto&& fn) {
+    for (int32_t u = P.block_lo[i]; u < P.block_lo[i + 1]; ++u) {
+      for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+        const int32_t v = ci[k];
+        const int32_t j = block_of(v);
+        if (j < i || (j == i && v < u)) continue;
+        const int64_t du = rp[u + 1] - rp[u], dv = rp[v + 1] - rp[v];
+        const bool u_small = du < dv || (du == dv && u < v);
+        fn(j, u_small ? u : v, u_small ? v : u, bucket_small(u_small ? du : dv));
+      }
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        for (int32_t i = t; i < K; i += nth)
+          for_edges_of_block(i, [&](int32_t j, int32_t, int32_t, int b) { cnt[(size_t)(pair_index(i, j) * NB + b)]++; });
+      });
+    for (auto& x : th) x.join();
+  }
+  std::vector<int64_t> off((size_t)(npairs * NB + 1), 0);
+  for (int64_t k = 0; k < npairs * NB; ++k) off[(size_t)k + 1] = off[(size_t)k] + cnt[(size_t)k];
+  if (off.back() != m) return fail(SCAN_E_GRAPH, "edge count %lld does not match nnz/2", (long long)off.back());
+  hipError_t e;
+  if ((e = hipHostMalloc((void**)&P.h_edges, sizeof(int2) * (size_t)std::max<int64_t>(m, 1), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&P.h_state, (size_t)std::max<int64_t>(m, 1), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&P.h_ecount, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&P.h_ci, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), hipHostMallocDefault)) != hipSuccess)
+    return fail_hip(e, "pinned host memory");
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        std::vector<int64_t> cur((size_t)NB);
+        for (int32_t i = t; i < K; i += nth) {
+          // cursors of the pairs (i, j >= i): written only by this thread
+          std::vector<int64_t> pc((size_t)((K - i) * NB));
+          for (int32_t j = i; j < K; ++j)
+            for (int b = 0; b < NB; ++b) pc[(size_t)((j - i) * NB + b)] = off[(size_t)(pair_index(i, j) * NB + b)];
+          for_edges_of_block(i, [&](int32_t j, int32_t su, int32_t lv, int b) {
+            P.h_edges[pc[(size_t)((j - i) * NB + b)]++] = make_int2(su, lv);
+          });
+        }
+      });
+    for (auto& x : th) x.join();
+  }
+  if (nnz > 0) memcpy(P.h_ci, ci, sizeof(int32_t) * (size_t)nnz);
+  // chunks: runs of one pair of at most chunk_cap edges
+  for (int32_t i = 0; i < K; ++i)
+    for (int32_t j = i; j < K; ++j) {
+      const int64_t pi = pair_index(i, j);
+      const int64_t b0 = off[(size_t)(pi * NB)], b1 = off[(size_t)(pi * NB + NB)];
+      for (int64_t c0 = b0; c0 < b1; c0 += chunk_cap) {
+        PartChunk C;
+        C.bi = i;
+        C.bj = j;
+        C.begin = c0;
+        C.end = std::min(b1, c0 + chunk_cap);
+        for (int b = 0; b <= kNumBuckets; ++b) {
+          const int64_t x = b < NB ? off[(size_t)(pi * NB + b)] : b1;
+          C.bucket_off[b] = std::min(std::max(x, C.begin), C.end);
+        }
+        P.chunks.push_back(C);
+      }
+    }
+  P.row_cap = row_cap;
+  P.chunk_cap = chunk_cap;
+  if ((e = hipMalloc((void**)&P.d_rows, sizeof(int32_t) * (size_t)std::max<int64_t>(row_cap, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_edges, sizeof(int2) * (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_state, (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_ecount, sizeof(int32_t) * (size_t)chunk_cap)) != hipSuccess)
+    return fail_hip(e, "device buffers");
+  g->partitioned = true;
+  g->m = m;
+  return SCAN_OK;
+}
+
+namespace {
+
+struct Streamer {
+  scan_graph* g;
+  hipStream_t s;
+  int32_t li = -1, lj = -1;
+  int64_t len_i = 0;
+
+  // Makes the rows of blocks i and j resident and returns the row mapping.
+  hipError_t rows(int32_t i, int32_t j, EdgeArgs& A) {
+    PartPlan& P = g->part;
+    const int32_t lo_i = P.block_lo[(size_t)i], hi_i = P.block_lo[(size_t)i + 1];
+    const int32_t lo_j = P.block_lo[(size_t)j], hi_j = P.block_lo[(size_t)j + 1];
+    hipError_t e = hipSuccess;
+    if (i != li) {
+      len_i = P.h_rp[(size_t)hi_i] - P.h_rp[(size_t)lo_i];
+      if (len_i > 0)
+        e = hipMemcpyAsync(P.d_rows, P.h_ci + P.h_rp[(size_t)lo_i], sizeof(int32_t) * (size_t)len_i,
+                           hipMemcpyHostToDevice, s);
+      P.h2d_bytes += 4ull * (uint64_t)len_i;
+      li = i;
+      lj = -1;
+    }
+    if (e == hipSuccess && j != i && j != lj) {
+      const int64_t len_j = P.h_rp[(size_t)hi_j] - P.h_rp[(size_t)lo_j];
+      if (len_j > 0)
+        e = hipMemcpyAsync(P.d_rows + len_i, P.h_ci + P.h_rp[(size_t)lo_j], sizeof(int32_t) * (size_t)len_j,
+                           hipMemcpyHostToDevice, s);
+      P.h2d_bytes += 4ull * (uint64_t)len_j;
+      lj = j;
+    }
+    A.ci = P.d_rows;
+    A.a_lo = lo_i;
+    A.a_hi = hi_i;
+    A.delta_a = P.h_rp[(size_t)lo_i];
+    A.delta_b = P.h_rp[(size_t)lo_j] - len_i;
+    return e;
+  }
+};
+
+}  // namespace
+
+int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_labels, uint8_t* d_roles,
+             hipStream_t s) {
+  PartPlan& P = g->part;
+  const bool timing = g->opts.timing != 0;
+  auto mark = [&](int k) {
+    if (timing) (void)hipEventRecord(g->ev[k], s);
+  };
+  P.h2d_bytes = 0;
+  const int32_t n = g->n;
+  HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
+  EdgeArgs A{};
+  A.rp = g->d_rp;
+  A.edges = P.d_edges;
+  A.state = P.d_state;
+  A.lower = g->d_lower;
+  A.upper = g->d_upper;
+  A.role = g->d_role;
+  A.parent = g->d_parent;
+  A.label = g->d_label;
+  A.stats = g->d_stats;
+  A.p = p;
+  A.q = q;
+  A.mu = mu;
+  A.pruning = g->opts.pruning;
+  mark(0);
+  launch_init(s, n, g->d_rp, mu, g->d_lower, g->d_upper, g->d_role, g->d_parent);
+  if (g->m > 0) memset(P.h_state, SIM_UNK, (size_t)g->m);
+  mark(1);
+  const int modes[3] = {MODE_CORES, MODE_MERGE, MODE_ATTACH};
+  for (int mi = 0; mi < 3; ++mi) {
+    const int mode = modes[mi];
+    if (mode == MODE_MERGE) {
+      mark(2);
+      launch_finalize_roles(s, n, mu, g->d_lower, g->d_role);
+      mark(3);
+      mark(4);
+    } else if (mode == MODE_ATTACH) {
+      mark(5);
+      launch_flatten(s, n, g->d_role, g->d_parent, g->d_label);
+      mark(6);
+    }
+    Streamer st{g, s};
+    for (const PartChunk& C : P.chunks) {
+      const int64_t ne = C.end - C.begin;
+      HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
+      HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
+              "edges H2D");
+      HIP_TRY(hipMemcpyAsync(P.d_state, P.h_state + C.begin, (size_t)ne, hipMemcpyHostToDevice, s), "state H2D");
+      P.h2d_bytes += 9ull * (uint64_t)ne;
+      if (mode == MODE_MERGE) launch_hook(s, ne, P.d_edges, P.d_state, g->d_role, g->d_parent);
+      for (int b = 0; b < kNumBuckets - 1; ++b) {
+        A.e_begin = C.bucket_off[b] - C.begin;
+        A.e_end = C.bucket_off[b + 1] - C.begin;
+        A.bucket = b;
+        launch_edges(s, mode, b, A);
+      }
+      if (mode != MODE_ATTACH)
+        HIP_TRY(hipMemcpyAsync(P.h_state + C.begin, P.d_state, (size_t)ne, hipMemcpyDeviceToHost, s), "state D2H");
+      // The next chunk overwrites the device buffers and the host reuses them
+      // only through stream order; the state copy back must land before the
+      // next pass reads P.h_state, which the synchronisation below ensures.
+    }
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+  mark(7);
+  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles);
+  mark(8);
+  HIP_TRY(hipGetLastError(), "kernel launch");
+  unsigned long long stv[ST_COUNT];
+  HIP_TRY(hipMemcpyAsync(stv, g->d_stats, sizeof(stv), hipMemcpyDeviceToHost, s), "stats copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  scan_stats& L = g->last;
+  memset(&L, 0, sizeof(L));
+  L.edges = g->m;
+  const int phase_of_mode[3] = {SCAN_PHASE_CORES, SCAN_PHASE_MERGE, SCAN_PHASE_ATTACH};
+  for (int md = 0; md < 3; ++md) {
+    L.evaluated[phase_of_mode[md]] = (int64_t)stv[ST_EVAL + md];
+    L.bounded[phase_of_mode[md]] = (int64_t)stv[ST_BOUND + md];
+    L.probes[phase_of_mode[md]] = (int64_t)stv[ST_PROBES + md];
+  }
+  for (int k = 0; k < kNumBuckets; ++k) {
+    L.cores_bucket_evaluated[k] = (int64_t)stv[ST_BUCKET_EVAL + k];
+    L.cores_bucket_probes[k] = (int64_t)stv[ST_BUCKET_PROBES + k];
+  }
+  L.h2d_bytes = (int64_t)P.h2d_bytes;
+  if (timing) {
+    float ms = 0;
+    for (int ph = 0; ph < SCAN_NUM_PHASES; ++ph) {
+      (void)hipEventElapsedTime(&ms, g->ev[ph], g->ev[ph + 1]);
+      L.ms_phase[ph] = ms;
+    }
+    (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[SCAN_NUM_PHASES]);
+    L.ms_total = ms;
+  }
+  return SCAN_OK;
+}
+
+int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
+  PartPlan& P = g->part;
+  P.h2d_bytes = 0;
+  HIP_TRY(hipMemsetAsync(g->d_stats, 0, sizeof(unsigned long long) * ST_COUNT, s), "hipMemsetAsync");
+  EdgeArgs A{};
+  A.rp = g->d_rp;
+  A.edges = P.d_edges;
+  A.edge_counts = P.d_ecount;
+  A.stats = g->d_stats;
+  A.p = 1;
+  A.q = 1;
+  A.mu = 2;
+  A.pruning = 0;
+  Streamer st{g, s};
+  for (const PartChunk& C : P.chunks) {
+    const int64_t ne = C.end - C.begin;
+    HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
+    HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
+            "edges H2D");
+    for (int b = 0; b < kNumBuckets - 1; ++b) {
+      A.e_begin = C.bucket_off[b] - C.begin;
+      A.e_end = C.bucket_off[b + 1] - C.begin;
+      A.bucket = b;
+      launch_edges(s, MODE_COUNTS, b, A);
+    }
+    HIP_TRY(hipMemcpyAsync(P.h_ecount + C.begin, P.d_ecount, sizeof(int32_t) * (size_t)ne, hipMemcpyDeviceToHost, s),
+            "counts D2H");
+  }
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  // per-edge counts to both arcs (CSR order)
+  const int64_t m = g->m;
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      for (int64_t k = t; k < m; k += nth) {
+        const int2 uv = P.h_edges[k];
+        const int32_t* ru = P.h_ci + P.h_rp[(size_t)uv.x];
+        const int32_t* rv = P.h_ci + P.h_rp[(size_t)uv.y];
+        const int64_t du = P.h_rp[(size_t)uv.x + 1] - P.h_rp[(size_t)uv.x];
+        const int64_t dv = P.h_rp[(size_t)uv.y + 1] - P.h_rp[(size_t)uv.y];
+        const int64_t pu = std::lower_bound(ru, ru + du, uv.y) - ru;
+        const int64_t pv = std::lower_bound(rv, rv + dv, uv.x) - rv;
+        h_counts[P.h_rp[(size_t)uv.x] + pu] = P.h_ecount[k];
+        h_counts[P.h_rp[(size_t)uv.y] + pv] = P.h_ecount[k];
+      }
+    });
+  for (auto& x : th) x.join();
+  g->last = scan_stats();
+  g->last.edges = m;
+  g->last.h2d_bytes = (int64_t)P.h2d_bytes;
+  return SCAN_OK;
+}
+
+}  // namespace scan

@@ -11,11 +11,13 @@ enum : uint8_t { ROLE_UNK = 0, ROLE_CORE = 1, ROLE_NONCORE = 2 };
 // Per-edge similarity state (Table 1: ?, S, !S).
 enum : uint8_t { SIM_UNK = 0, SIM_YES = 1, SIM_NO = 2 };
 
-// Degree buckets of the oriented edge list, keyed by the smaller degree d_s:
-//   0: d_s <= 4, 1: <= 8, 2: <= 16, 3: <= 32, 4: <= 64  (group of 4..64 lanes per edge)
-//   5: d_s > 64                                          (one wave per edge, tiled)
-constexpr int kNumBuckets = 6;
-constexpr int kGroupLanes[5] = {4, 8, 16, 32, 64};
+// Degree buckets of the oriented edge list, keyed by the smaller degree d_s
+// and the larger degree d_l:
+//   0: d_s <= 4, 1: <= 8, 2: <= 16, 3: <= 32, 4: <= 64   (groups of 4..64 lanes per edge)
+//   5: d_s > 64, d_l <= kHubMinDegree                     (one wave per edge, tiled)
+//   6: d_s > 64, d_l >  kHubMinDegree                     (LDS-hash kernel, by larger side)
+constexpr int kNumBuckets = 7;
+constexpr int kHubMinDegree = 512;
 
 __host__ __device__ inline int bucket_of(int64_t ds) {
   return ds <= 4 ? 0 : ds <= 8 ? 1 : ds <= 16 ? 2 : ds <= 32 ? 3 : ds <= 64 ? 4 : 5;
@@ -35,8 +37,8 @@ enum : int {
   ST_BOUND = 4,     // + phase: decided by the degree bound
   ST_PROBES = 8,    // + phase: smaller-list elements consumed
   ST_BUCKET_EVAL = 12,   // + bucket (cores phase only)
-  ST_BUCKET_PROBES = 18, // + bucket
-  ST_COUNT = 24
+  ST_BUCKET_PROBES = 19, // + bucket
+  ST_COUNT = 26
 };
 // Mode -> stats phase slot (0..3).
 __host__ __device__ inline int mode_slot(int mode) { return mode; }
@@ -53,6 +55,24 @@ __host__ __device__ inline uint32_t closed_needed(uint64_t p, uint64_t q, uint64
   return (uint32_t)((s + q - 1) / q);           // (c q)^2 >= X  <=>  c q >= ceil(sqrt(X))
 }
 
+// LDS-hash kernel of the last bucket (d_u > 64): one job = up to kHubJobEdges
+// in-edges (u, v) of one larger side v, consecutive in the edge list.
+constexpr int kHubJobEdges = 4096; // in-edges per job
+constexpr int64_t kHubJobWork = 1 << 20;  // smaller-list elements per job (bound on probes)
+constexpr int kHubBlock = 512;     // threads per block of the LDS-hash kernel
+constexpr int kHubBatch = 256;     // survivors per table fill
+constexpr int kHubGroup = 16;      // lanes streaming one survivor
+constexpr int kHubUnroll = 4;      // elements per lane per step
+constexpr int kHubChunk = 256;     // elements of one survivor handed to a group at a time
+constexpr int kHubLog2Slots = 14;  // LDS hash table: 16384 int32 slots = 64 KiB
+constexpr int kHubSlots = 1 << kHubLog2Slots;
+constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
+struct HubJob {
+  int64_t begin;  // first edge of the job
+  int32_t v;      // common larger side
+  int32_t count;  // edges in the job (<= kHubJobEdges)
+};
+
 struct EdgeArgs {
   const int64_t* rp;
   const int32_t* ci;
@@ -64,35 +84,65 @@ struct EdgeArgs {
   uint8_t* role;
   int32_t* parent;
   int32_t* label;
-  int32_t* counts;    // MODE_COUNTS: per arc output
+  int32_t* counts;       // MODE_COUNTS: per arc output (optional)
+  int32_t* edge_counts;  // MODE_COUNTS: per oriented edge output (optional)
   unsigned long long* stats;
   uint64_t p, q;
   int32_t mu;
   int32_t pruning;
   int32_t bucket;
+  // Row placement: row of x starts at ci + rp[x] - delta, with delta_a for
+  // a_lo <= x < a_hi and delta_b otherwise (0 and 0 when the graph is resident).
+  int32_t a_lo, a_hi;
+  int64_t delta_a, delta_b;
+  // Batch of graphs: graph id of every vertex and per-graph eps = gp/gq, mu
+  // (null for a single graph, which uses p, q, mu above).
+  const int32_t* gid;
+  const uint64_t* gp;
+  const uint64_t* gq;
+  const int32_t* gmu;
 };
 
 // Launchers (kernels.hip)
 void launch_init(hipStream_t s, int32_t n, const int64_t* rp, int32_t mu, int32_t* lower,
-                 int32_t* upper, uint8_t* role, int32_t* parent);
+                 int32_t* upper, uint8_t* role, int32_t* parent, const int32_t* gid = nullptr,
+                 const int32_t* gmu = nullptr);
 void launch_edges(hipStream_t s, int mode, int bucket, const EdgeArgs& a);
+// Same with an explicit lane-group width (4, 8, 16, 32 or 64), any bucket.
+void launch_edges_lanes(hipStream_t s, int mode, int lanes, const EdgeArgs& a);
+// Last bucket through the LDS-hash kernel; counter must be zero on entry,
+// worklist holds one int32 per edge of the bucket.
+void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
+                unsigned long long* counter, int32_t* worklist);
+void launch_zero_u64(hipStream_t s, unsigned long long* p, int n);
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
-void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role);
+void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,
+                           const int32_t* gid = nullptr, const int32_t* gmu = nullptr);
 void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,
                  const uint8_t* role, int32_t* parent);
 void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* parent, int32_t* label);
 void launch_output(hipStream_t s, int32_t n, const uint8_t* role, const int32_t* label,
-                   int32_t* out_labels, uint8_t* out_roles);
+                   int32_t* out_labels, uint8_t* out_roles, const int32_t* gid = nullptr,
+                   const int32_t* gbase = nullptr);
+
+// Serving: one query from cached per-edge closed counts (no intersections).
+void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
+                        const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
+                        uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
+                        int32_t* out_labels, uint8_t* out_roles);
 
 // Layout (layout.hip)
 struct LayoutResult {
   int64_t bucket_off[kNumBuckets + 1];
+  int64_t hub_jobs;
   int32_t max_degree;
   int32_t error;  // 0 or bit mask of validation failures
 };
-// Validates the CSR and builds the oriented, bucketed edge list, allocated
-// here (*d_edges, bucket_off[kNumBuckets] entries; caller frees).
-hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* d_rp,
-                        const int32_t* d_ci, int validate, int2** d_edges, LayoutResult* out);
+// Validates the CSR and builds the oriented, bucketed edge list and the job
+// table of the last bucket, both allocated here (caller frees):
+//   *d_edges: bucket_off[kNumBuckets] entries, *d_jobs: hub_jobs entries.
+hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
+                        const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
+                        int2** d_edges, HubJob** d_jobs, LayoutResult* out);
 
 }  // namespace scan

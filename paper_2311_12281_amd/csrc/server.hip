@@ -1,0 +1,478 @@
+// Serving: graphs stay resident with the exact closed count of every edge,
+// and (graph, eps, mu) queries are answered by re-thresholding those counts
+// (no intersection), which needs only streaming passes over the edges.
+//
+// Continuous batching: a dispatcher thread admits queued requests onto free
+// slots as soon as slots free up; each slot owns a HIP stream, per-query
+// scratch and pinned output buffers, so requests that arrive while others are
+// running overlap on the device.  Completion is detected with events, results
+// are copied out of the slot's pinned buffers and the slot is reused.
+//
+// Memory admission: a graph is made resident only if its footprint (graph
+// layout plus cached counts plus, when it is the largest, the slots' scratch)
+// fits the budget; otherwise it is kept in host memory and its queries run
+// through scan_graph_create with the remaining budget and scan_run.
+#include "graph.h"
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServedGraph {
+  int32_t n = 0;
+  int64_t nnz = 0, m = 0;
+  bool resident = false;
+  scan_graph* g = nullptr;       // resident: device layout
+  int32_t* d_ecount = nullptr;   // resident: closed count per oriented edge
+  uint64_t bytes = 0;            // device bytes held while resident
+  std::vector<int64_t> h_rp;     // non-resident: host copy
+  std::vector<int32_t> h_ci;
+  int inflight = 0;
+  bool removing = false;
+};
+
+struct Request {
+  int64_t id = 0;
+  int32_t gid = 0;
+  int64_t p = 1, q = 1;
+  int32_t mu = 2;
+  Clock::time_point t_submit, t_done;
+  int status = 1;  // 1 pending/running, 0 ok, < 0 error
+  std::string error;
+  std::vector<int32_t> labels;
+  std::vector<uint8_t> roles;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  int32_t cap_n = 0;
+  int64_t cap_m = 0;
+  int32_t *d_lower = nullptr, *d_parent = nullptr, *d_label = nullptr, *d_out_labels = nullptr;
+  uint8_t *d_role = nullptr, *d_state = nullptr, *d_out_roles = nullptr;
+  int32_t* h_labels = nullptr;  // pinned
+  uint8_t* h_roles = nullptr;   // pinned
+  std::shared_ptr<Request> req;  // running request, or null
+};
+
+uint64_t slot_bytes(int32_t n, int64_t m) { return 18ull * (uint64_t)n + (uint64_t)m; }
+
+uint64_t graph_bytes(int32_t n, int64_t nnz) {
+  const uint64_t m = (uint64_t)nnz / 2;
+  // layout (row_ptr, col_idx, oriented edges, worklist) + per-run state + cached counts
+  return 8ull * ((uint64_t)n + 1) + 4ull * nnz + 8ull * m + 4ull * m + 22ull * n + 1ull * m + 4ull * m;
+}
+
+void free_slot_buffers(Slot& s) {
+  void* d[] = {s.d_lower, s.d_parent, s.d_label, s.d_out_labels, s.d_role, s.d_state, s.d_out_roles};
+  for (void* p : d)
+    if (p) (void)hipFree(p);
+  if (s.h_labels) (void)hipHostFree(s.h_labels);
+  if (s.h_roles) (void)hipHostFree(s.h_roles);
+  s.d_lower = s.d_parent = s.d_label = s.d_out_labels = nullptr;
+  s.d_role = s.d_state = s.d_out_roles = nullptr;
+  s.h_labels = nullptr;
+  s.h_roles = nullptr;
+  s.cap_n = 0;
+  s.cap_m = 0;
+}
+
+hipError_t alloc_slot_buffers(Slot& s, int32_t n, int64_t m) {
+  free_slot_buffers(s);
+  const size_t N = (size_t)(n > 0 ? n : 1), M = (size_t)(m > 0 ? m : 1);
+  hipError_t e;
+  if ((e = hipMalloc((void**)&s.d_lower, 4 * N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_parent, 4 * N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_label, 4 * N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_out_labels, 4 * N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_role, N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_out_roles, N)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&s.d_state, M)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&s.h_labels, 4 * N, hipHostMallocDefault)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&s.h_roles, N, hipHostMallocDefault)) != hipSuccess) return e;
+  s.cap_n = n;
+  s.cap_m = m;
+  return hipSuccess;
+}
+
+}  // namespace
+
+struct scan_server {
+  scan_opts opts{};
+  uint64_t budget = 0;  // 0 = no cap
+  uint64_t resident_bytes = 0;
+  std::mutex mu;
+  std::condition_variable cv_work;  // dispatcher wake-up
+  std::condition_variable cv_done;  // waiters
+  std::map<int32_t, std::unique_ptr<ServedGraph>> graphs;
+  int32_t next_gid = 0;
+  int64_t next_req = 1;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::map<int64_t, std::shared_ptr<Request>> requests;
+  std::vector<Slot> slots;
+  int32_t slot_n = 0;  // slot scratch capacity
+  int64_t slot_m = 0;
+  int64_t completed = 0;
+  bool stop = false;
+  bool pause_dispatch = false;  // set while slot buffers are being resized
+  std::thread worker;
+};
+
+namespace {
+
+// Host path for a graph kept outside the device (over the admission limit):
+// a budgeted scan_graph_create + scan_run.  Called without the server lock.
+void run_fallback(const ServedGraph* G, uint64_t budget, const scan_opts& base, Request* r) {
+  scan_opts o = base;
+  o.hip_stream = nullptr;
+  o.device_budget_bytes = budget;
+  scan_graph* g = nullptr;
+  r->labels.resize((size_t)G->n);
+  r->roles.resize((size_t)G->n);
+  int rc = scan_graph_create(G->n, G->nnz, G->h_rp.data(), G->h_ci.data(), &o, &g);
+  if (rc == SCAN_OK) {
+    rc = scan_run(g, r->p, r->q, r->mu, r->labels.data(), r->roles.data());
+    scan_graph_destroy(g);
+  }
+  r->status = rc;
+  if (rc != SCAN_OK) r->error = scan_last_error();
+}
+
+// Starts one request on a free slot (server lock held).  Returns false if
+// the request finished at once (with an error).
+bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& r, ServedGraph* G) {
+  int64_t p = r->p, q = r->q;
+  int64_t a = p, b = q;
+  while (b) { int64_t t = a % b; a = b; b = t; }
+  p /= a;
+  q /= a;
+  scan_graph* g = G->g;
+  if (G->n > slot.cap_n || G->m > slot.cap_m) {
+    r->status = SCAN_E_NOMEM;
+    r->error = "slot scratch smaller than the graph";
+    return false;
+  }
+  launch_rethreshold(slot.stream, G->n, G->m, g->d_rp, g->d_edges, G->d_ecount, (uint64_t)p, (uint64_t)q,
+                     r->mu, slot.d_lower, slot.d_role, slot.d_parent, slot.d_label, slot.d_state,
+                     slot.d_out_labels, slot.d_out_roles);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && G->n > 0)
+    e = hipMemcpyAsync(slot.h_labels, slot.d_out_labels, 4 * (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
+  if (e == hipSuccess && G->n > 0)
+    e = hipMemcpyAsync(slot.h_roles, slot.d_out_roles, (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
+  if (e == hipSuccess) e = hipEventRecord(slot.done, slot.stream);
+  if (e != hipSuccess) {
+    r->status = SCAN_E_DEVICE;
+    r->error = hipGetErrorString(e);
+    return false;
+  }
+  G->inflight++;
+  slot.req = r;
+  return true;
+}
+
+void finish(scan_server* S, const std::shared_ptr<Request>& r) {
+  r->t_done = Clock::now();
+  S->completed++;
+  S->cv_done.notify_all();
+}
+
+void worker_loop(scan_server* S) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    bool progress = false;
+    // completions
+    for (auto& slot : S->slots) {
+      if (!slot.req) continue;
+      const hipError_t q = hipEventQuery(slot.done);
+      if (q == hipErrorNotReady) continue;
+      auto r = slot.req;
+      slot.req.reset();
+      ServedGraph* G = S->graphs[r->gid].get();
+      G->inflight--;
+      if (q == hipSuccess) {
+        r->labels.assign(slot.h_labels, slot.h_labels + G->n);
+        r->roles.assign(slot.h_roles, slot.h_roles + G->n);
+        r->status = SCAN_OK;
+      } else {
+        r->status = SCAN_E_DEVICE;
+        r->error = hipGetErrorString(q);
+      }
+      finish(S, r);
+      progress = true;
+    }
+    // admissions: as many queued requests as there are free slots
+    for (auto& slot : S->slots) {
+      if (S->pause_dispatch || slot.req || S->pending.empty()) continue;
+      auto r = S->pending.front();
+      S->pending.pop_front();
+      progress = true;
+      auto it = S->graphs.find(r->gid);
+      ServedGraph* G = it == S->graphs.end() ? nullptr : it->second.get();
+      if (!G) {
+        r->status = SCAN_E_INVAL;
+        r->error = "unknown graph id";
+        finish(S, r);
+      } else if (!G->resident) {
+        G->inflight++;
+        const uint64_t budget = S->budget > S->resident_bytes ? S->budget - S->resident_bytes : 1;
+        const scan_opts base = S->opts;
+        lk.unlock();
+        run_fallback(G, budget, base, r.get());
+        lk.lock();
+        G->inflight--;
+        finish(S, r);
+        break;  // slots may have changed state meanwhile
+      } else if (!launch_on_slot(S, slot, r, G)) {
+        finish(S, r);
+      }
+    }
+    bool busy = false;
+    for (auto& slot : S->slots) busy = busy || (bool)slot.req;
+    if (S->stop && !busy && S->pending.empty()) break;
+    if (!progress) {
+      if (busy) {
+        // poll the running slots without holding the lock
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      } else {
+        S->cv_work.wait(lk, [&] { return S->stop || (!S->pending.empty() && !S->pause_dispatch); });
+      }
+    }
+  }
+}
+
+// Stop admissions and wait (lock held) until no slot is running, so that
+// slot buffers can be replaced; the caller clears pause_dispatch afterwards.
+void drain(scan_server* S, std::unique_lock<std::mutex>& lk) {
+  S->pause_dispatch = true;
+  S->cv_done.wait(lk, [&] {
+    for (auto& s : S->slots)
+      if (s.req) return false;
+    return true;
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+int scan_server_create(const scan_opts* opts, int32_t num_slots, scan_server** out) {
+  if (!out) return fail(SCAN_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (num_slots < 1 || num_slots > 64) return fail(SCAN_E_INVAL, "num_slots must be in 1..64");
+  auto* S = new (std::nothrow) scan_server();
+  if (!S) return fail(SCAN_E_NOMEM, "host allocation failed");
+  if (opts) S->opts = *opts;
+  else scan_opts_default(&S->opts);
+  S->opts.hip_stream = nullptr;
+  S->budget = S->opts.device_budget_bytes;
+  S->slots.resize((size_t)num_slots);
+  for (auto& s : S->slots) {
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+      for (auto& t : S->slots) {
+        if (t.stream) (void)hipStreamDestroy(t.stream);
+        if (t.done) (void)hipEventDestroy(t.done);
+      }
+      delete S;
+      return fail(SCAN_E_DEVICE, "cannot create slot streams");
+    }
+  }
+  S->worker = std::thread(worker_loop, S);
+  *out = S;
+  return SCAN_OK;
+}
+
+int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t* row_ptr,
+                          const int32_t* col_idx, int32_t* gid_out) {
+  if (!S || !gid_out) return fail(SCAN_E_INVAL, "NULL argument");
+  if (n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return fail(SCAN_E_INVAL, "bad CSR arguments");
+  auto G = std::make_unique<ServedGraph>();
+  G->n = n;
+  G->nnz = nnz;
+  G->m = nnz / 2;
+  const uint64_t gbytes = graph_bytes(n, nnz);
+  bool resident;
+  {
+    // admission: reserve the graph's bytes and what the slots would grow by
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int32_t new_n = n > S->slot_n ? n : S->slot_n;
+    const int64_t new_m = G->m > S->slot_m ? G->m : S->slot_m;
+    const uint64_t grow = S->slots.size() * (slot_bytes(new_n, new_m) - slot_bytes(S->slot_n, S->slot_m));
+    resident = S->budget == 0 || S->resident_bytes + gbytes + grow <= S->budget;
+    if (resident) S->resident_bytes += gbytes;
+  }
+  if (resident) {
+    scan_opts o = S->opts;
+    o.device_budget_bytes = 0;
+    scan_graph* g = nullptr;
+    int rc = scan_graph_create(n, nnz, row_ptr, col_idx, &o, &g);
+    if (rc == SCAN_OK && g->m > 0) {
+      hipError_t e = hipMalloc((void**)&G->d_ecount, sizeof(int32_t) * (size_t)g->m);
+      if (e != hipSuccess) {
+        rc = fail_hip(e, "hipMalloc counts");
+      } else {
+        std::lock_guard<std::mutex> glk(g->lock);
+        rc = run_counts(g, nullptr, G->d_ecount, g->stream);
+      }
+    }
+    if (rc != SCAN_OK) {
+      if (G->d_ecount) (void)hipFree(G->d_ecount);
+      if (g) scan_graph_destroy(g);
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->resident_bytes -= gbytes;
+      return rc;
+    }
+    G->g = g;
+    G->resident = true;
+    G->bytes = gbytes;
+  } else {
+    G->h_rp.assign(row_ptr, row_ptr + n + 1);
+    if (nnz > 0) G->h_ci.assign(col_idx, col_idx + nnz);
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (resident && (n > S->slot_n || G->m > S->slot_m)) {
+    const int32_t new_n = n > S->slot_n ? n : S->slot_n;
+    const int64_t new_m = G->m > S->slot_m ? G->m : S->slot_m;
+    drain(S, lk);
+    hipError_t e = hipSuccess;
+    for (auto& s : S->slots)
+      if (e == hipSuccess) e = alloc_slot_buffers(s, new_n, new_m);
+    if (e != hipSuccess) {
+      for (auto& s : S->slots) (void)alloc_slot_buffers(s, S->slot_n, S->slot_m);
+      S->pause_dispatch = false;
+      S->cv_work.notify_one();
+      S->resident_bytes -= gbytes;
+      lk.unlock();
+      if (G->d_ecount) (void)hipFree(G->d_ecount);
+      scan_graph_destroy(G->g);
+      return fail_hip(e, "slot scratch");
+    }
+    S->resident_bytes += S->slots.size() * (slot_bytes(new_n, new_m) - slot_bytes(S->slot_n, S->slot_m));
+    S->slot_n = new_n;
+    S->slot_m = new_m;
+    S->pause_dispatch = false;
+    S->cv_work.notify_one();
+  }
+  const int32_t gid = S->next_gid++;
+  S->graphs[gid] = std::move(G);
+  *gid_out = gid;
+  return SCAN_OK;
+}
+
+int scan_server_remove_graph(scan_server* S, int32_t gid) {
+  if (!S) return fail(SCAN_E_INVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->graphs.find(gid);
+  if (it == S->graphs.end()) return fail(SCAN_E_INVAL, "unknown graph id %d", gid);
+  ServedGraph* G = it->second.get();
+  G->removing = true;
+  S->cv_done.wait(lk, [&] {
+    if (G->inflight > 0) return false;
+    for (auto& r : S->pending)
+      if (r->gid == gid) return false;
+    return true;
+  });
+  if (G->resident) {
+    if (G->d_ecount) (void)hipFree(G->d_ecount);
+    scan_graph_destroy(G->g);
+    S->resident_bytes -= G->bytes;
+  }
+  S->graphs.erase(it);
+  return SCAN_OK;
+}
+
+int scan_server_submit(scan_server* S, int32_t gid, int64_t eps_num, int64_t eps_den, int32_t mu,
+                       int64_t* req_out) {
+  if (!S || !req_out) return fail(SCAN_E_INVAL, "NULL argument");
+  if (eps_num < 1 || eps_den < eps_num) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den");
+  if (mu < 2) return fail(SCAN_E_INVAL, "mu must be >= 2");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->graphs.find(gid);
+  if (it == S->graphs.end() || it->second->removing) return fail(SCAN_E_INVAL, "unknown graph id %d", gid);
+  const ServedGraph* G = it->second.get();
+  if (G->resident) {
+    int64_t a = eps_num, b = eps_den;
+    while (b) { int64_t t = a % b; a = b; b = t; }
+    const unsigned __int128 q = (unsigned __int128)(eps_den / a);
+    if (q * (unsigned __int128)((uint64_t)G->g->max_degree + 1) >= ((unsigned __int128)1 << 32))
+      return fail(SCAN_E_RANGE, "eps denominator too large for this graph's maximum degree");
+  }
+  auto r = std::make_shared<Request>();
+  r->id = S->next_req++;
+  r->gid = gid;
+  r->p = eps_num;
+  r->q = eps_den;
+  r->mu = mu;
+  r->t_submit = Clock::now();
+  S->requests[r->id] = r;
+  S->pending.push_back(r);
+  *req_out = r->id;
+  S->cv_work.notify_one();
+  return SCAN_OK;
+}
+
+int scan_server_wait(scan_server* S, int64_t req, int32_t* labels, uint8_t* roles, double* latency_ms) {
+  if (!S) return fail(SCAN_E_INVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->requests.find(req);
+  if (it == S->requests.end()) return fail(SCAN_E_INVAL, "unknown request %lld", (long long)req);
+  auto r = it->second;
+  S->cv_done.wait(lk, [&] { return r->status != 1; });
+  S->requests.erase(req);
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (r->status != SCAN_OK) return fail(r->status, "%s", r->error.c_str());
+  if (labels && !r->labels.empty()) memcpy(labels, r->labels.data(), 4 * r->labels.size());
+  if (roles && !r->roles.empty()) memcpy(roles, r->roles.data(), r->roles.size());
+  return SCAN_OK;
+}
+
+int scan_server_info(scan_server* S, uint64_t* resident_bytes, int32_t* graphs, int32_t* resident_graphs,
+                     int64_t* completed) {
+  if (!S) return fail(SCAN_E_INVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int32_t res = 0;
+  for (auto& kv : S->graphs) res += kv.second->resident ? 1 : 0;
+  if (resident_bytes) *resident_bytes = S->resident_bytes;
+  if (graphs) *graphs = (int32_t)S->graphs.size();
+  if (resident_graphs) *resident_graphs = res;
+  if (completed) *completed = S->completed;
+  return SCAN_OK;
+}
+
+int scan_server_destroy(scan_server* S) {
+  if (!S) return SCAN_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& kv : S->graphs) {
+    ServedGraph* G = kv.second.get();
+    if (G->resident) {
+      if (G->d_ecount) (void)hipFree(G->d_ecount);
+      scan_graph_destroy(G->g);
+    }
+  }
+  for (auto& s : S->slots) {
+    free_slot_buffers(s);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  delete S;
+  return SCAN_OK;
+}
+
+}  // extern "C"

@@ -238,3 +238,40 @@ def test_rmat22_full_size():
     note("rmat22 generate")
     g = gg.rmat(22, 16, seed=2)
     check_graph(g, [((1, 5), 5), ((1, 2), 5), ((4, 5), 5), ((1, 10), 5)], "rmat22", timing=True)
+
+
+def windowed_hub_graph(seed=5, hub_deg=20000, heavy=300, extra=150):
+    """Vertex 0 is adjacent to 1..hub_deg (several LDS windows); vertices
+    1..heavy get `extra` more neighbours inside 1..hub_deg, so their edges to
+    the hub have a smaller side of degree > 64 and share many neighbours with
+    it across every window."""
+    rng = np.random.default_rng(seed)
+    edges = [(0, i) for i in range(1, hub_deg + 1)]
+    for u in range(1, heavy + 1):
+        for w in rng.choice(np.arange(1, hub_deg + 1), size=extra, replace=False):
+            if int(w) != u:
+                edges.append((u, int(w)))
+    return gg.from_edges(hub_deg + 1, edges)
+
+
+def test_windowed_hub():
+    g = windowed_hub_graph()
+    check_graph(g, [((1, 10), 2), ((1, 5), 3), ((1, 20), 5), ((1, 100), 2)], "windowed-hub")
+
+
+@pytest.mark.parametrize("name,gen", [
+    ("rmat16", lambda: gg.rmat(16, 16, seed=2)),
+    ("windowed-hub", windowed_hub_graph),
+    ("planted-A", lambda: gg.planted(10000, 50, 0.15, 0.0005, 1)),
+])
+def test_strategies_identical(name, gen):
+    """The LDS-hash kernel and the binary-search kernel give the same counts
+    and the same clustering."""
+    g = gen()
+    note("strategies", name)
+    with S.Graph.from_csr(g, strategy=0) as A, S.Graph.from_csr(g, strategy=1) as B:
+        assert np.array_equal(A.similarity(), B.similarity())
+        for (p, q), mu in [((1, 10), 3), ((1, 5), 5), ((1, 2), 2)]:
+            la, ra = A.run(p, q, mu)
+            lb, rb = B.run(p, q, mu)
+            assert np.array_equal(ra, rb) and np.array_equal(la, lb), (name, p, q, mu)

@@ -1,0 +1,81 @@
+"""Serving (cached closed counts + re-thresholding, continuous batching):
+every answer must equal the oracle's and a plain scan_run, alone and in a mix
+of concurrent requests on several graphs."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2311_12281_amd as S
+from gpu_helpers import assert_same, note
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serving_matches_oracle_alone_and_in_mix():
+    graphs = [gg.rmat(14, 16, seed=11), gg.planted(10000, 50, 0.15, 0.0005, 1),
+              gg.rmat(12, 8, seed=12), gg.chung_lu(30000, 20.0, 2.1, 1500.0, seed=13)]
+    counts = [oracle.counts(g, threads=oracle.max_threads()) for g in graphs]
+    rng = np.random.default_rng(5)
+    queries = [(int(rng.integers(len(graphs))), int(rng.integers(1, 10)), 10, int(rng.integers(2, 21)))
+               for _ in range(120)]
+    note("serving: 4 graphs, 120 queries, 4 slots")
+    with S.Server(num_slots=4) as srv:
+        gids = [srv.add(g) for g in graphs]
+        # alone: one request at a time
+        alone = {}
+        for gi, p, q, mu in queries[:20]:
+            r = srv.submit(gids[gi], p, q, mu)
+            alone[(gi, p, q, mu)] = srv.wait(r, gids[gi])[:2]
+        # in the mix: everything submitted at once
+        reqs = [(srv.submit(gids[gi], p, q, mu), gi, p, q, mu) for gi, p, q, mu in queries]
+        for r, gi, p, q, mu in reqs:
+            l, ro, lat = srv.wait(r, gids[gi])
+            assert lat >= 0
+            ol, orr = oracle.cluster(graphs[gi], counts[gi], p, q, mu)
+            assert_same(l, ro, ol, orr, f"served graph {gi} eps={p}/{q} mu={mu}")
+            if (gi, p, q, mu) in alone:
+                al, ar = alone[(gi, p, q, mu)]
+                assert np.array_equal(al, l) and np.array_equal(ar, ro)
+        info = srv.info()
+        assert info["graphs"] == 4 and info["resident_graphs"] == 4
+        assert info["completed"] == len(queries) + 20
+
+
+def test_serving_equals_scan_run():
+    g = gg.rmat(16, 16, seed=2)
+    note("serving vs scan_run rmat16")
+    with S.Server(num_slots=2) as srv, S.Graph.from_csr(g) as G:
+        gid = srv.add(g)
+        for p, q, mu in [(1, 5, 5), (1, 2, 5), (4, 5, 5), (1, 10, 3), (1, 10, 2)]:
+            l, r, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
+            gl, gr = G.run(p, q, mu)
+            assert np.array_equal(l, gl) and np.array_equal(r, gr)
+
+
+def test_serving_add_remove_and_errors():
+    note("serving add/remove/errors")
+    g1 = gg.planted(3000, 10, 0.2, 0.002, 3)
+    g2 = gg.rmat(15, 16, seed=4)  # larger: grows the slots' scratch
+    with S.Server(num_slots=3) as srv:
+        a = srv.add(g1)
+        ra = [srv.submit(a, 1, 5, 4) for _ in range(6)]
+        b = srv.add(g2)
+        rb = [srv.submit(b, 1, 10, 3) for _ in range(6)]
+        la = [srv.wait(r, a)[:2] for r in ra]
+        lb = [srv.wait(r, b)[:2] for r in rb]
+        ol, orr = oracle.scan(g1, 1, 5, 4)
+        for l, r in la:
+            assert_same(l, r, ol, orr, "g1")
+        ol, orr = oracle.scan(g2, 1, 10, 3, threads=oracle.max_threads())
+        for l, r in lb:
+            assert_same(l, r, ol, orr, "g2")
+        srv.remove(a)
+        with pytest.raises(S.ScanError) as ei:
+            srv.submit(a, 1, 5, 4)
+        assert ei.value.code == S.SCAN_E_INVAL
+        with pytest.raises(S.ScanError):
+            srv.submit(b, 0, 5, 4)
+        with pytest.raises(S.ScanError):
+            srv.submit(b, 1, 5, 1)
+        assert srv.info()["graphs"] == 1
