@@ -18,6 +18,15 @@ with HIP events on the library's stream, against 8 TB/s.
 
 cpu_baseline: the oracle (not tuned) on the host cores, on the same graph at
 eps = 1/2, mu = 5: closed counts of every edge plus clustering.
+
+Other workloads (their own JSON line, not the default):
+  --workload partitioned  Chung-Lu power-law graph under a device budget,
+                          partition-based path vs in-memory path;
+  --workload serving      resident R-MAT graphs, Poisson query stream,
+                          served (cached counts, continuous batching) vs
+                          plain per-query scan_run: p50/p99 latency, edges/s;
+  --workload batched      many planted-partition graphs in one captured
+                          launch vs one scan_run per graph.
 """
 from __future__ import annotations
 
@@ -51,12 +60,28 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched"])
+    ap.add_argument("--cl-n", type=int, default=50_000_000, help="partitioned: Chung-Lu vertices")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="partitioned: device budget")
+    ap.add_argument("--serve-graphs", type=int, default=16)
+    ap.add_argument("--serve-scale-min", type=int, default=14)
+    ap.add_argument("--serve-scale-max", type=int, default=20)
+    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--batch-count", type=int, default=10000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr, flush=True)
         sys.exit(2)
+
+    if args.workload == "partitioned":
+        return bench_partitioned(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import graphgen as gg
     import paper_2311_12281_amd as S
@@ -196,6 +221,211 @@ def main():
         "per_eps": per_eps,
     }
     print(json.dumps(line), flush=True)
+
+
+def _line(metric, value, unit, config, **rest):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "higher_is_better": True,
+         "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": config}
+    d.update(rest)
+    print(json.dumps(d), flush=True)
+
+
+def bench_partitioned(args):
+    """Chung-Lu (exponent 2.1, mean degree 30, degree cap 1e6) under a device
+    budget: the partition-based path streams blocks over the host link; the
+    in-memory path on the same graph gives the reference result and time."""
+    import graphgen as gg
+    import paper_2311_12281_amd as S
+
+    t = time.perf_counter()
+    g = gg.chung_lu(args.cl_n, 30.0, 2.1, 1.0e6, seed=3)
+    log(f"Chung-Lu n={g.n} m={g.m} max_deg={int(g.degrees().max())} generated in {time.perf_counter() - t:.1f}s")
+    budget = int(args.budget_gb * (1 << 30))
+    t = time.perf_counter()
+    P = S.Graph.from_csr(g, budget=budget, timing=True)
+    create_p = time.perf_counter() - t
+    t = time.perf_counter()
+    M = S.Graph.from_csr(g, timing=True)
+    create_m = time.perf_counter() - t
+    rows = []
+    exact = True
+    for (p, q), mu in [((1, 2), 10), ((1, 10), 3)]:
+        t = time.perf_counter()
+        pl, pr = P.run(p, q, mu)
+        tp = time.perf_counter() - t
+        st = P.stats()
+        t = time.perf_counter()
+        ml, mr = M.run(p, q, mu)
+        tm = time.perf_counter() - t
+        same = bool(np.array_equal(pl, ml) and np.array_equal(pr, mr))
+        exact = exact and same
+        rows.append({"eps": f"{p}/{q}", "mu": mu, "partitioned_s": tp, "in_memory_s": tm,
+                     "partitioned_edges_per_s": g.m / tp, "in_memory_edges_per_s": g.m / tm,
+                     "h2d_GB": st["h2d_bytes"] / 1e9, "h2d_GB_per_s": st["h2d_bytes"] / 1e9 / tp,
+                     "identical_to_in_memory": same, "cores": int((pr == 1).sum()),
+                     "borders": int((pr == 2).sum())})
+        log(rows[-1])
+    P.close()
+    M.close()
+    _line("edges/s (|E|/solve) exact-match, partition-based path", g.m / rows[0]["partitioned_s"], "edges/s",
+          {"workload": f"chunglu_n{g.n}_budget{args.budget_gb}GB", "n": g.n, "m": g.m, "eps": "1/2", "mu": 10},
+          identical_to_in_memory=exact, create_partitioned_s=create_p, create_in_memory_s=create_m, runs=rows)
+
+
+def bench_serving(args):
+    """Resident R-MAT graphs; a Poisson stream of (graph, eps = k/10, mu)
+    queries at a fixed rate.  Served: cached closed counts, re-thresholding,
+    continuous batching over slots.  Plain: one scan_run per query, first come
+    first served.  Latency = completion - arrival."""
+    import threading
+
+    import graphgen as gg
+    import paper_2311_12281_amd as S
+
+    rng = np.random.default_rng(5)
+    graphs = []
+    for k in range(args.serve_graphs):
+        sc = int(rng.integers(args.serve_scale_min, args.serve_scale_max + 1))
+        ef = int(rng.integers(8, 33))
+        graphs.append(gg.rmat(sc, ef, seed=100 + k))
+    log(f"{len(graphs)} R-MAT graphs, {sum(g.m for g in graphs)} edges in total")
+    queries = [(int(rng.integers(len(graphs))), int(rng.integers(1, 10)), 10, int(rng.integers(2, 21)))
+               for _ in range(args.serve_queries)]
+    srv = S.Server(num_slots=args.serve_slots)
+    t = time.perf_counter()
+    gids = [srv.add(g) for g in graphs]
+    add_s = time.perf_counter() - t
+    plain = [S.Graph.from_csr(g) for g in graphs]
+
+    def served_saturation():
+        t0 = time.perf_counter()
+        reqs = [srv.submit(gids[gi], p, q, mu) for gi, p, q, mu in queries]
+        for r, (gi, _, _, _) in zip(reqs, queries):
+            srv.wait(r, gids[gi])
+        return len(queries) / (time.perf_counter() - t0)
+
+    def plain_saturation():
+        t0 = time.perf_counter()
+        for gi, p, q, mu in queries[:200]:
+            plain[gi].run(p, q, mu)
+        return 200 / (time.perf_counter() - t0)
+
+    sat_served = served_saturation()
+    sat_plain = plain_saturation()
+    log(f"saturation: served {sat_served:.1f} q/s, plain {sat_plain:.1f} q/s")
+
+    def run_served(qps):
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(queries)))
+        lat = [0.0] * len(queries)
+        reqs = [None] * len(queries)
+        start = time.perf_counter()
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for k in range(len(queries)):
+                ready.acquire()
+                _, _, ms = srv.wait(reqs[k], gids[queries[k][0]])
+                lat[k] = ms
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        for k, (gi, p, q, mu) in enumerate(queries):
+            d = start + arr[k] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            reqs[k] = srv.submit(gids[gi], p, q, mu)
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - start
+        return np.array(lat), wall
+
+    def run_plain(qps, count):
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
+        lat = []
+        start = time.perf_counter()
+        for k, (gi, p, q, mu) in enumerate(queries[:count]):
+            d = start + arr[k] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            plain[gi].run(p, q, mu)
+            lat.append((time.perf_counter() - start - arr[k]) * 1e3)
+        return np.array(lat), time.perf_counter() - start
+
+    out = {}
+    edges = float(sum(graphs[gi].m for gi, _, _, _ in queries))
+    for frac in (0.5, 0.9):
+        qps = frac * sat_served
+        ls, ws = run_served(qps)
+        cnt = min(len(queries), max(50, int(qps * 10)))  # plain path: bounded run at the same rate
+        lp, wp = run_plain(qps, cnt)
+        out[f"{frac}x"] = {
+            "qps": qps,
+            "served_p50_ms": float(np.percentile(ls, 50)), "served_p99_ms": float(np.percentile(ls, 99)),
+            "served_edges_per_s": edges / ws,
+            "plain_p50_ms": float(np.percentile(lp, 50)), "plain_p99_ms": float(np.percentile(lp, 99)),
+            "plain_edges_per_s": float(sum(graphs[gi].m for gi, _, _, _ in queries[:cnt])) / wp,
+            "plain_queries": cnt}
+        log(f"{frac}x: {out[f'{frac}x']}")
+    # exactness: served answers equal scan_run for a sample
+    exact = True
+    for gi, p, q, mu in queries[:50]:
+        l, r, _ = srv.wait(srv.submit(gids[gi], p, q, mu), gids[gi])
+        gl, gr = plain[gi].run(p, q, mu)
+        exact = exact and bool(np.array_equal(l, gl) and np.array_equal(r, gr))
+    for G in plain:
+        G.close()
+    srv.close()
+    _line("queries/s at saturation, served (cached counts, continuous batching)", sat_served, "queries/s",
+          {"workload": f"serving_{len(graphs)}_rmat_s{args.serve_scale_min}-{args.serve_scale_max}",
+           "queries": len(queries), "slots": args.serve_slots},
+          plain_saturation_qps=sat_plain, add_graphs_s=add_s, exact_match=exact, poisson=out)
+
+
+def bench_batched(args):
+    """Many planted-partition graphs (n log-uniform in [100, 20000], mean
+    degree U[8, 64], 5-200 blocks, per-graph eps in {1/5..4/5}, mu in 2..10):
+    one captured launch for the batch vs one scan_run per graph."""
+    import graphgen as gg
+    import oracle
+    import paper_2311_12281_amd as S
+
+    t = time.perf_counter()
+    graphs, specs = gg.planted_batch(args.batch_count, seed=4)
+    eps = [s.eps for s in specs]
+    mus = [s.mu for s in specs]
+    m = sum(g.m for g in graphs)
+    log(f"{len(graphs)} graphs, {sum(g.n for g in graphs)} vertices, {m} edges, generated in "
+        f"{time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    B = S.Batch(graphs, eps, mus, autotune=True)
+    create_s = time.perf_counter() - t
+    lanes, hub = B.config()
+    B.run()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        labels, roles = B.run(replay=True)
+    batch_s = (time.perf_counter() - t) / args.steps
+    # plain: one resident graph per input, one scan_run each
+    plain = [S.Graph.from_csr(g) for g in graphs]
+    t = time.perf_counter()
+    res = [G.run(p, q, mu) for G, (p, q), mu in zip(plain, eps, mus)]
+    plain_s = time.perf_counter() - t
+    for G in plain:
+        G.close()
+    ls, rs = B.split(labels), B.split(roles)
+    same = all(np.array_equal(a[0], b) and np.array_equal(a[1], c) for a, b, c in zip(res, ls, rs))
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(graphs), size=min(200, len(graphs)), replace=False)
+    oracle_ok = True
+    for k in sample:
+        ol, orr = oracle.scan(graphs[k], *eps[k], mus[k])
+        oracle_ok = oracle_ok and bool(np.array_equal(ol, ls[k]) and np.array_equal(orr, rs[k]))
+    B.close()
+    _line("edges/s (|E|/solve) exact-match, batched", m / batch_s, "edges/s",
+          {"workload": f"planted_batch_{len(graphs)}", "graphs": len(graphs), "m": m},
+          ms_per_batch=batch_s * 1e3, plain_edges_per_s=m / plain_s, plain_ms=plain_s * 1e3,
+          identical_to_plain=same, oracle_sample_exact=oracle_ok, autotuned_lanes=lanes, hub=hub,
+          create_s=create_s)
 
 
 if __name__ == "__main__":

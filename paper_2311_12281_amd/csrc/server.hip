@@ -130,21 +130,23 @@ struct scan_server {
 namespace {
 
 // Host path for a graph kept outside the device (over the admission limit):
-// a budgeted scan_graph_create + scan_run.  Called without the server lock.
-void run_fallback(const ServedGraph* G, uint64_t budget, const scan_opts& base, Request* r) {
+// a budgeted scan_graph_create + scan_run.  Called without the server lock;
+// the result goes to the caller's buffers and is published under the lock.
+int run_fallback(const ServedGraph* G, uint64_t budget, const scan_opts& base, int64_t p, int64_t q, int32_t mu,
+                 std::vector<int32_t>& labels, std::vector<uint8_t>& roles, std::string& error) {
   scan_opts o = base;
   o.hip_stream = nullptr;
   o.device_budget_bytes = budget;
   scan_graph* g = nullptr;
-  r->labels.resize((size_t)G->n);
-  r->roles.resize((size_t)G->n);
+  labels.resize((size_t)G->n);
+  roles.resize((size_t)G->n);
   int rc = scan_graph_create(G->n, G->nnz, G->h_rp.data(), G->h_ci.data(), &o, &g);
   if (rc == SCAN_OK) {
-    rc = scan_run(g, r->p, r->q, r->mu, r->labels.data(), r->roles.data());
+    rc = scan_run(g, p, q, mu, labels.data(), roles.data());
     scan_graph_destroy(g);
   }
-  r->status = rc;
-  if (rc != SCAN_OK) r->error = scan_last_error();
+  if (rc != SCAN_OK) error = scan_last_error();
+  return rc;
 }
 
 // Starts one request on a free slot (server lock held).  Returns false if
@@ -226,9 +228,18 @@ void worker_loop(scan_server* S) {
         G->inflight++;
         const uint64_t budget = S->budget > S->resident_bytes ? S->budget - S->resident_bytes : 1;
         const scan_opts base = S->opts;
+        const int64_t p = r->p, q = r->q;
+        const int32_t mu = r->mu;
+        std::vector<int32_t> labels;
+        std::vector<uint8_t> roles;
+        std::string error;
         lk.unlock();
-        run_fallback(G, budget, base, r.get());
+        const int rc = run_fallback(G, budget, base, p, q, mu, labels, roles, error);
         lk.lock();
+        r->labels.swap(labels);
+        r->roles.swap(roles);
+        r->error = error;
+        r->status = rc;
         G->inflight--;
         finish(S, r);
         break;  // slots may have changed state meanwhile

@@ -79,3 +79,25 @@ def test_serving_add_remove_and_errors():
         with pytest.raises(S.ScanError):
             srv.submit(b, 1, 5, 1)
         assert srv.info()["graphs"] == 1
+
+
+def test_serving_admission_falls_back_to_partitioned_path():
+    """A graph that does not fit the server's device budget stays on the host;
+    its queries run through the budgeted (partition-based) path with the same
+    results."""
+    small = gg.rmat(12, 8, seed=21)
+    big = gg.rmat(15, 16, seed=22)
+    g_small = 8 * (small.n + 1) + 4 * small.nnz + 17 * (small.nnz // 2) + 22 * small.n
+    slots = 2 * (18 * big.n + big.nnz // 2)
+    budget = g_small + slots + 30 * big.n + (6 << 20)
+    note("serving admission budget", budget)
+    with S.Server(num_slots=2, budget=budget) as srv:
+        a = srv.add(small)
+        b = srv.add(big)
+        info = srv.info()
+        assert info["graphs"] == 2 and info["resident_graphs"] == 1
+        for gid, g in ((a, small), (b, big)):
+            for p, q, mu in [(1, 5, 4), (1, 10, 3)]:
+                l, r, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
+                ol, orr = oracle.scan(g, p, q, mu, threads=oracle.max_threads())
+                assert_same(l, r, ol, orr, f"admission gid={gid} eps={p}/{q} mu={mu}")
