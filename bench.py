@@ -69,7 +69,13 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--batch-count", type=int, default=10000)
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy calibration")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs of this bench")
+    ap.add_argument("--pmc-kernel", default="k_hub<0>")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -145,6 +151,19 @@ def main():
         })
         log(f"eps={p}/{q}: {per_eps[-1]}")
 
+    # HBM reference: a plain streaming copy of --copy-mib MiB (read once, written once); the byte
+    # counters of the dominant kernel are scaled by what they read for this copy
+    copy_bytes = args.copy_mib << 20
+    csrc_ = S.scan_device_alloc(copy_bytes)
+    cdst_ = S.scan_device_alloc(copy_bytes)
+    copy_ms = S.scan_device_copy(cdst_, csrc_, copy_bytes, iters=5)
+    S.scan_device_free(csrc_)
+    S.scan_device_free(cdst_)
+    copy_gbps = 2.0 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    log(f"streaming copy {args.copy_mib} MiB: {copy_ms:.3f} ms -> {copy_gbps:.0f} GB/s")
+    dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
+    traffic = _traffic_from_profile(dom_kernel)
+
     # PCIe-inclusive rate (host outputs), reported beside the value
     t = time.perf_counter()
     host_out = [G.run(p, q, MU) for (p, q) in EPS_SET]
@@ -209,8 +228,9 @@ def main():
                    "mu": MU, "step": "one scan_run_device per eps, graph resident"},
         "exact_match": exact,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"cores pass, degree bucket {dom}",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"{dom_kernel}: cores pass, degree bucket {dom}",
+                     "copy_gbps": copy_gbps,
                      "launch_ms": float(ms_b[dom] / launches),
                      "alg_bytes_per_launch": float(bytes_b[dom] / launches)},
         "cpu_baseline": cpu,
@@ -221,6 +241,98 @@ def main():
         "per_eps": per_eps,
     }
     print(json.dumps(line), flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_hub_cores_rmat22.md")
+KERNEL_SOURCES = ["kernels.hip", "layout.hip", "api.hip", "scan_internal.h"]
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_12281_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when there is
+    none for this kernel or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for ln in fh:
+            if ln.startswith("- ") and ": " in ln:
+                k, v = ln[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != _kernel_source_hash():
+        log(f"traffic: counter summary is for {kv.get('kernel')} / sources "
+            f"{kv.get('kernel_sources_sha256')}, current {kernel} / {_kernel_source_hash()}: null")
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _pmc_rows(d):
+    """(kernel name, counter, value) per dispatch from rocprofv3 counter CSVs under d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def _per_dispatch_mean(rows, counter, match):
+    per = {}
+    for did, name, c, v in rows:
+        if c == counter and match(name):
+            per[did] = per.get(did, 0.0) + v
+    return (sum(per.values()) / len(per), len(per)) if per else (None, 0)
+
+
+def summarize_pmc(args):
+    """Markdown summary of HBM bytes per launch for the dominant kernel, scaled by the copy."""
+    fetch_rows = _pmc_rows(args.summarize_pmc[0])
+    write_rows = _pmc_rows(args.summarize_pmc[1])
+    is_copy = lambda nm: "k_copy16" in nm
+    want = args.pmc_kernel
+    is_k = lambda nm: want in nm
+    cf, ncf = _per_dispatch_mean(fetch_rows, "FETCH_SIZE", is_copy)
+    cw, ncw = _per_dispatch_mean(write_rows, "WRITE_SIZE", is_copy)
+    kf, nkf = _per_dispatch_mean(fetch_rows, "FETCH_SIZE", is_k)
+    kw, nkw = _per_dispatch_mean(write_rows, "WRITE_SIZE", is_k)
+    if None in (cf, cw, kf, kw):
+        sys.exit(f"missing dispatches: copy {ncf}/{ncw}, {want} {nkf}/{nkw}")
+    copy_kib = (args.copy_mib << 20) / 1024.0
+    sf, sw = copy_kib / cf, copy_kib / cw
+    traffic = (kf * sf + kw * sw) * 1024.0
+    print(f"""# HBM traffic of {want} (cores pass, LDS-hash bucket), R-MAT scale 22
+
+Commands (from the repository root on the MI355X host, each its own run):
+
+```
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
+python bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --pmc-kernel '{want}'
+```
+
+The copy kernel `k_copy16` moves {args.copy_mib} MiB (read once, written once) per dispatch; its
+counters scale the kernel's (KiB per dispatch, mean over dispatches).
+
+| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |
+|---|---|---|---|
+| k_copy16 | {ncf}/{ncw} | {cf:.0f} | {cw:.0f} |
+| {want} | {nkf}/{nkw} | {kf:.0f} | {kw:.0f} |
+
+- copy scale (fetch, write): {sf:.4f}, {sw:.4f}
+- kernel: `{want}`
+- kernel_sources_sha256: `{_kernel_source_hash()}`
+- traffic_bytes_per_launch: {traffic:.0f}
+""")
 
 
 def _line(metric, value, unit, config, **rest):

@@ -258,6 +258,15 @@ int scan_device_free(void* ptr);
 int scan_memcpy_d2h(void* dst, const void* src, uint64_t bytes);
 int scan_memcpy_h2d(void* dst, const void* src, uint64_t bytes);
 
+/* Device-to-device copy of `bytes` (a multiple of 16; src and dst device
+ * pointers, 16-byte aligned, not overlapping) by a plain streaming kernel,
+ * launched `iters` >= 1 times in a row on its own stream; *avg_ms (may be NULL)
+ * receives the mean kernel time.  Not part of the clustering path: it is the
+ * reference against which hardware byte counters and HBM bandwidth of the
+ * clustering kernels are calibrated.  SCAN_E_INVAL on a bad size, alignment
+ * or iteration count. */
+int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, float* avg_ms);
+
 /* Thread-local description of the last error, valid until the next call. */
 const char* scan_last_error(void);
 

@@ -447,4 +447,31 @@ int scan_memcpy_h2d(void* dst, const void* src, uint64_t bytes) {
   return SCAN_OK;
 }
 
+int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, float* avg_ms) {
+  if (!dst || !src || (bytes & 15) || iters < 1 || (((uintptr_t)dst | (uintptr_t)src) & 15))
+    return fail(SCAN_E_INVAL, "scan_device_copy: bytes must be a multiple of 16, pointers 16-byte aligned, iters >= 1");
+  const uintptr_t d = (uintptr_t)dst, sp = (uintptr_t)src;
+  if (bytes && d < sp + bytes && sp < d + bytes) return fail(SCAN_E_INVAL, "scan_device_copy: buffers overlap");
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  int rc = SCAN_OK;
+  float ms = 0.f;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = fail(SCAN_E_DEVICE, "hipEventCreate failed");
+  } else {
+    (void)hipEventRecord(e0, s);
+    for (int32_t i = 0; i < iters; ++i) launch_copy16(s, src, dst, (int64_t)(bytes / 16));
+    (void)hipEventRecord(e1, s);
+    hipError_t err = hipStreamSynchronize(s);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) rc = fail_hip(err, "scan_device_copy");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc == SCAN_OK && avg_ms) *avg_ms = ms / (float)iters;
+  return rc;
+}
+
 }  // extern "C"

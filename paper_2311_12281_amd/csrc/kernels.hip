@@ -647,6 +647,14 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Plain streaming copy, 16 bytes per lane per step: the reference kernel against which hardware
+// byte counters are scaled (every byte is read once and written once).
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_init(int32_t n, const int64_t* rp, int32_t mu, const int32_t* gid, const int32_t* gmu,
                        int32_t* lower, int32_t* upper, uint8_t* role, int32_t* parent) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -840,6 +848,10 @@ void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, 
     case MODE_ATTACH: k_hub<MODE_ATTACH><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
     default: k_hub<MODE_COUNTS><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
   }
+}
+
+void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16) {
+  if (n16 > 0) k_copy16<<<blocks_for(n16, 256, 16384), 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
 }
 
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n) {

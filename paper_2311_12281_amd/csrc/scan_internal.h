@@ -115,6 +115,7 @@ void launch_edges_lanes(hipStream_t s, int mode, int lanes, const EdgeArgs& a);
 void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
                 unsigned long long* counter, int32_t* worklist);
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n);
+void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16);
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
 void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,
                            const int32_t* gid = nullptr, const int32_t* gmu = nullptr);

@@ -217,6 +217,27 @@ def test_device_entry_points():
                 S.scan_device_free(p)
 
 
+def test_device_copy_calibration_kernel():
+    note("scan_device_copy")
+    nbytes = (3 << 20) + 48
+    src = np.random.default_rng(5).integers(0, 256, nbytes, dtype=np.uint8)
+    ds = S.scan_device_alloc(nbytes)
+    dd = S.scan_device_alloc(nbytes)
+    try:
+        S.scan_memcpy_h2d(ds, src, nbytes)
+        ms = S.scan_device_copy(dd, ds, nbytes, iters=2)
+        out = np.empty(nbytes, np.uint8)
+        S.scan_memcpy_d2h(out, dd, nbytes)
+        assert np.array_equal(out, src) and ms > 0
+        with pytest.raises(S.ScanError):
+            S.scan_device_copy(dd, ds, nbytes - 8)
+        with pytest.raises(S.ScanError):
+            S.scan_device_copy(dd, ds, nbytes, iters=0)
+    finally:
+        S.scan_device_free(ds)
+        S.scan_device_free(dd)
+
+
 def test_stats_are_consistent():
     g = gg.rmat(16, 16, seed=2)
     note("stats rmat16")
