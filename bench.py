@@ -379,9 +379,13 @@ def bench_partitioned(args):
         log(rows[-1])
     P.close()
     M.close()
+    link = S.scan_h2d_rate(1 << 30, 5)
+    log(f"pinned H2D copy rate: {link / 1e9:.1f} GB/s")
+    for r in rows:
+        r["h2d_frac_of_link"] = r["h2d_GB_per_s"] * 1e9 / link
     _line("edges/s (|E|/solve) exact-match, partition-based path", g.m / rows[0]["partitioned_s"], "edges/s",
           {"workload": f"chunglu_n{g.n}_budget{args.budget_gb}GB", "n": g.n, "m": g.m, "eps": "1/2", "mu": 10},
-          identical_to_in_memory=exact, create_partitioned_s=create_p, create_in_memory_s=create_m, runs=rows)
+          identical_to_in_memory=exact, h2d_link_GB_per_s=link / 1e9, create_partitioned_s=create_p, create_in_memory_s=create_m, runs=rows)
 
 
 def bench_serving(args):

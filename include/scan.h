@@ -267,6 +267,14 @@ int scan_memcpy_h2d(void* dst, const void* src, uint64_t bytes);
  * or iteration count. */
 int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, float* avg_ms);
 
+/* Host-to-device link rate: copies `bytes` from a pinned host buffer into a
+ * device buffer (both allocated and freed inside the call) `iters` >= 1 times
+ * with hipMemcpyAsync and stores bytes per second of the mean copy in *h2d_bps.
+ * The reference rate for the partitioned path, which streams from pinned host
+ * memory.  SCAN_E_INVAL on bytes == 0 or iters < 1, SCAN_E_NOMEM if either
+ * buffer cannot be allocated. */
+int scan_h2d_rate(uint64_t bytes, int32_t iters, double* h2d_bps);
+
 /* Thread-local description of the last error, valid until the next call. */
 const char* scan_last_error(void);
 

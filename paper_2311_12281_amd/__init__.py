@@ -28,7 +28,7 @@ EXPORTED = [
     "scan_opts_default", "scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
     "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_eps_threshold",
     "scan_last_stats", "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h",
-    "scan_memcpy_h2d", "scan_device_copy", "scan_last_error", "scan_version",
+    "scan_memcpy_h2d", "scan_device_copy", "scan_h2d_rate", "scan_last_error", "scan_version",
     "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph", "scan_server_submit",
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
@@ -117,6 +117,7 @@ def lib():
         L.scan_memcpy_d2h.argtypes = [vp, vp, u64]
         L.scan_memcpy_h2d.argtypes = [vp, vp, u64]
         L.scan_device_copy.argtypes = [vp, vp, u64, i32, P(ctypes.c_float)]
+        L.scan_h2d_rate.argtypes = [u64, i32, P(ctypes.c_double)]
         L.scan_server_create.argtypes = [P(scan_opts), i32, P(vp)]
         L.scan_server_add_graph.argtypes = [vp, i32, i64, vp, vp, P(i32)]
         L.scan_server_remove_graph.argtypes = [vp, i32]
@@ -135,7 +136,7 @@ def lib():
         for name in ("scan_graph_create", "scan_graph_destroy", "scan_graph_info", "scan_run",
                      "scan_run_device", "scan_similarity", "scan_similarity_device", "scan_last_stats",
                      "scan_device_alloc", "scan_device_free", "scan_memcpy_d2h", "scan_memcpy_h2d",
-                     "scan_device_copy", "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph",
+                     "scan_device_copy", "scan_h2d_rate", "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph",
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
                      "scan_batch_destroy", "scan_run_batch"):
@@ -279,6 +280,13 @@ def scan_device_copy(dst: int, src: int, nbytes: int, iters: int = 1) -> float:
     _check(lib().scan_device_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), int(nbytes), int(iters),
                                   ctypes.byref(ms)))
     return float(ms.value)
+
+
+def scan_h2d_rate(nbytes: int = 1 << 30, iters: int = 5) -> float:
+    """Pinned host-to-device copy rate in bytes per second."""
+    r = ctypes.c_double()
+    _check(lib().scan_h2d_rate(int(nbytes), int(iters), ctypes.byref(r)))
+    return float(r.value)
 
 
 class Graph:

@@ -474,4 +474,43 @@ int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, 
   return rc;
 }
 
+int scan_h2d_rate(uint64_t bytes, int32_t iters, double* h2d_bps) {
+  if (!bytes || iters < 1 || !h2d_bps) return fail(SCAN_E_INVAL, "scan_h2d_rate: bytes > 0, iters >= 1, h2d_bps required");
+  void* h = nullptr;
+  void* d = nullptr;
+  if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCAN_E_NOMEM, "scan_h2d_rate: hipHostMalloc of %llu bytes failed", (unsigned long long)bytes);
+  }
+  if (hipMalloc(&d, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(h);
+    return fail(SCAN_E_NOMEM, "scan_h2d_rate: hipMalloc of %llu bytes failed", (unsigned long long)bytes);
+  }
+  memset(h, 1, bytes);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SCAN_OK;
+  float ms = 0.f;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    rc = fail(SCAN_E_DEVICE, "scan_h2d_rate: stream or event creation failed");
+  } else {
+    hipError_t err = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);  // warm-up
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int32_t i = 0; i < iters && err == hipSuccess; ++i) err = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) rc = fail_hip(err, "scan_h2d_rate");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(d);
+  (void)hipHostFree(h);
+  if (rc == SCAN_OK) *h2d_bps = ms > 0 ? (double)bytes * iters / (ms * 1e-3) : 0.0;
+  return rc;
+}
+
 }  // extern "C"

@@ -233,6 +233,9 @@ def test_device_copy_calibration_kernel():
             S.scan_device_copy(dd, ds, nbytes - 8)
         with pytest.raises(S.ScanError):
             S.scan_device_copy(dd, ds, nbytes, iters=0)
+        assert S.scan_h2d_rate(1 << 22, 2) > 0
+        with pytest.raises(S.ScanError):
+            S.scan_h2d_rate(0, 1)
     finally:
         S.scan_device_free(ds)
         S.scan_device_free(dd)
