@@ -63,6 +63,7 @@ class Oracle:
         lib.oracle_scan.argtypes = [i32, vp, vp, i64, i64, i32, ctypes.c_int, vp, vp, vp]
         lib.oracle_scan.restype = ctypes.c_int
         lib.oracle_cluster.argtypes = [i32, vp, vp, vp, i64, i64, i32, vp, vp]
+        lib.oracle_hub_outlier.argtypes = [i32, vp, vp, vp, vp]
         lib.oracle_cluster.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         self.lib = lib
@@ -122,6 +123,18 @@ class Oracle:
             raise ValueError(f"oracle_cluster failed with code {rc}")
         return labels[:n], roles[:n]
 
+    def hub_outlier(self, g, labels: np.ndarray, roles: np.ndarray) -> np.ndarray:
+        """Roles with every unclassified vertex split into hub (3) or outlier (4), Def 2.7."""
+        n, rp, ci = self._arrays(g)
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        out = np.array(roles, dtype=np.uint8, copy=True)
+        if n == 0:
+            return out
+        rc = self.lib.oracle_hub_outlier(n, _vp(rp), _vp(ci), _vp(lab), _vp(out))
+        if rc != 0:
+            raise ValueError(f"oracle_hub_outlier failed with code {rc}")
+        return out
+
     def max_threads(self) -> int:
         return int(self.lib.oracle_max_threads())
 
@@ -158,6 +171,10 @@ def scan(g, p, q, mu, threads: int = 1, want_counts: bool = False):
 
 def cluster(g, counts, p, q, mu):
     return default().cluster(g, counts, p, q, mu)
+
+
+def hub_outlier(g, labels, roles):
+    return default().hub_outlier(g, labels, roles)
 
 
 def max_threads() -> int:

@@ -57,6 +57,8 @@
 #define ROLE_UNCLASSIFIED 0
 #define ROLE_CORE 1
 #define ROLE_BORDER 2
+#define ROLE_HUB 3     /* Def 2.7 */
+#define ROLE_OUTLIER 4
 
 /* Position of x in the sorted row, or -1. */
 static int64_t row_find(const int32_t* row, int64_t len, int32_t x) {
@@ -230,6 +232,29 @@ int oracle_cluster(int32_t n, const int64_t* rp, const int32_t* ci, const int32_
     labels[v] = best;
   }
   free(sim); free(core); free(queue);
+  return OR_OK;
+}
+
+/* Def 2.7: a vertex in no cluster is a hub when its neighbours lie in two or
+ * more clusters, and an outlier otherwise.  A neighbour's cluster is the label
+ * it was given (its own cluster for a core, the minimum label for a border),
+ * which is how the classification step of the paper (Alg. 4) reads it.  roles
+ * are updated in place: every ROLE_UNCLASSIFIED vertex becomes ROLE_HUB or
+ * ROLE_OUTLIER; labels stay -1 for both. */
+int oracle_hub_outlier(int32_t n, const int64_t* rp, const int32_t* ci, const int32_t* labels,
+                       uint8_t* roles) {
+  if (n < 0 || !labels || !roles) return OR_INVAL;
+  for (int32_t u = 0; u < n; ++u) {
+    if (roles[u] != ROLE_UNCLASSIFIED) continue;
+    int32_t first = -1, distinct = 0;
+    for (int64_t i = rp[u]; i < rp[u + 1] && distinct < 2; ++i) {
+      const int32_t c = labels[ci[i]];
+      if (c < 0) continue;
+      if (first < 0) { first = c; distinct = 1; }
+      else if (c != first) distinct = 2;
+    }
+    roles[u] = distinct >= 2 ? ROLE_HUB : ROLE_OUTLIER;
+  }
   return OR_OK;
 }
 

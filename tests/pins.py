@@ -26,7 +26,9 @@ import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components
 
 import graphgen as gg
-from bruteforce import brute_scan, closed_count as bf_closed_count
+from bruteforce import brute_scan, closed_count as bf_closed_count, closed_sets as bf_closed_sets
+
+HUB, OUTLIER = 3, 4
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 EPS_GRID = [(1, 10), (1, 5), (1, 3), (1, 2), (2, 3), (3, 4), (4, 5), (1, 1)]
@@ -62,6 +64,12 @@ def check_paper_example(orc):
     sims = [int(w) for w, c in zip(row, cnt[g.row_ptr[0]:g.row_ptr[1]])
             if orc.similar(int(c), deg[0] + 1, deg[w] + 1, p, q)]
     assert sorted([0] + sims) == fx["expected_eps_neighbourhood_v0"]
+    # Example 2.1 / Def 2.7: v8 is a hub (neighbours v2 and v9 in two clusters), v3 v5 v6 outliers
+    ho = orc.hub_outlier(g, labels, roles)
+    assert sorted(np.flatnonzero(ho == HUB).tolist()) == fx["expected_hubs"]
+    assert sorted(np.flatnonzero(ho == OUTLIER).tolist()) == fx["expected_outliers"]
+    keep = roles != 0
+    assert np.array_equal(ho[keep], roles[keep])
 
 
 def cycle(n):
@@ -136,10 +144,47 @@ def check_closed_forms(orc):
     # mu = 4 leaves cores 2 and 4 only, and 3 is a border of both clusters
     # (minimum label 2 wins).
     g = gg.from_edges(7, [(0, 1), (0, 2), (1, 2), (4, 5), (4, 6), (5, 6), (2, 3), (3, 4)])
+    check_hub_outlier_closed_form(orc)
     lab, rol = orc.scan(g, 1, 2, 3)
     assert rol.tolist() == [1] * 7 and lab.tolist() == [0] * 7
     lab, rol = orc.scan(g, 1, 2, 4)
     assert rol.tolist() == [2, 2, 1, 2, 1, 2, 2] and lab.tolist() == [2, 2, 2, 2, 4, 4, 4]
+
+
+def check_hub_outlier_closed_form(orc):
+    """Two triangles {0,1,2} and {4,5,6} bridged by 3 (edges 2-3, 3-4), a pendant 7 on 0 and an
+    isolated 8.  At eps = 3/4, mu = 3: sigma(0,2) = 3/sqrt(16) = 3/4 exactly (similar), the other
+    triangle edges are 3/sqrt(12) or 1, sigma(2,3) = sigma(3,4) = 2/sqrt(12) < 3/4 and sigma(0,7)
+    = 2/sqrt(8) < 3/4.  So the triangles are clusters 0 and 4, vertex 3 touches both (hub), the
+    pendant touches one (outlier) and the isolated vertex none (outlier), Def 2.7."""
+    g = gg.from_edges(9, [(0, 1), (0, 2), (1, 2), (4, 5), (4, 6), (5, 6), (2, 3), (3, 4), (0, 7)])
+    lab, rol = orc.scan(g, 3, 4, 3)
+    assert rol.tolist() == [1, 1, 1, 0, 1, 1, 1, 0, 0]
+    assert lab.tolist() == [0, 0, 0, -1, 4, 4, 4, -1, -1]
+    ho = orc.hub_outlier(g, lab, rol)
+    assert ho.tolist() == [1, 1, 1, HUB, 1, 1, 1, OUTLIER, OUTLIER]
+    # at mu = 4 nothing is a core: no clusters, every vertex an outlier
+    lab, rol = orc.scan(g, 3, 4, 4)
+    assert orc.hub_outlier(g, lab, rol).tolist() == [OUTLIER] * 9
+
+
+def expected_hub_outlier(n, edges, labels, roles, clusters):
+    """Def 2.7 from the brute force's clusters, two ways: (assigned) a neighbour's cluster is the
+    label it was given; (literal) a neighbour counts in every cluster that holds it.  They differ
+    only next to a border that lies in several clusters."""
+    _, nbr = bf_closed_sets(n, edges)
+    member = [{min(w for w in C if roles[w] == 1) for C in clusters if v in C} for v in range(n)]
+    assigned, literal = list(roles), list(roles)
+    for u in range(n):
+        if roles[u] != 0:
+            continue
+        a = {labels[w] for w in nbr[u] if labels[w] >= 0}
+        lit = set().union(*[member[w] for w in nbr[u]]) if nbr[u] else set()
+        assigned[u] = HUB if len(a) >= 2 else OUTLIER
+        literal[u] = HUB if len(lit) >= 2 else OUTLIER
+        if all(len(member[w]) <= 1 for w in nbr[u]):
+            assert assigned[u] == literal[u]
+    return assigned, literal
 
 
 def _edges_of(n, mask):
@@ -157,10 +202,13 @@ def check_against_bruteforce(orc, n, edges, grid=None, literal=False):
             assert cnt[k] == want, (n, edges, u, v)
             assert orc.closed_count(g, u, v) == want
     for (p, q), mu in (grid or [(e, m) for e in EPS_GRID for m in MU_GRID]):
-        labels, roles, _, _ = brute_scan(n, edges, p, q, mu, literal_subsets=literal)
+        labels, roles, clusters, hub = brute_scan(n, edges, p, q, mu, literal_subsets=literal)
         ol, orr = orc.scan(g, p, q, mu)
         assert orr.tolist() == roles, (n, edges, p, q, mu, orr.tolist(), roles)
         assert ol.tolist() == labels, (n, edges, p, q, mu, ol.tolist(), labels)
+        assigned, lit = expected_hub_outlier(n, edges, labels, roles, clusters)
+        assert [HUB if h else (OUTLIER if r == 0 else r) for h, r in zip(hub, roles)] == lit
+        assert orc.hub_outlier(g, ol, orr).tolist() == assigned, (n, edges, p, q, mu)
 
 
 def check_bruteforce_exhaustive(orc, nmax=5, literal_upto=4):

@@ -29,6 +29,9 @@ MUTANTS = {
     "border_ignores_similarity": ("if (core[u] && sim[i] && (best", "if (core[u] && (best"),
     "twin_arc_not_written": ("counts[rp[v] + row_find(ci + rp[v], dv, u)] = (int32_t)c;", ""),
     "closed_merge_off_by_one": ("if (k < at) return row[k];", "if (k <= at) return row[k];"),
+    "hub_needs_one_cluster": ("else if (c != first) distinct = 2;", "else distinct = 2;"),
+    "hub_counts_unclustered_neighbours": ("if (c < 0) continue;", ""),
+    "hub_relabels_clustered": ("if (roles[u] != ROLE_UNCLASSIFIED) continue;", ""),
     "validate_allows_asymmetry": ("if (row_find(ci + rp[v], rp[v + 1] - rp[v], u) < 0) return OR_GRAPH;",
                                   ""),
 }
