@@ -50,7 +50,12 @@ enum scan_status {
   SCAN_E_DEVICE = -5  /* HIP runtime error (no GPU, launch failure, ...) */
 };
 
-enum scan_role { SCAN_UNCLASSIFIED = 0, SCAN_CORE = 1, SCAN_BORDER = 2 };
+enum scan_role { SCAN_UNCLASSIFIED = 0, SCAN_CORE = 1, SCAN_BORDER = 2,
+                 /* with scan_opts.hub_outlier set, vertices in no cluster are
+                    split by Def 2.7: a hub has neighbours in two or more
+                    clusters (a border counts in the cluster it was given),
+                    an outlier does not */
+                 SCAN_HUB = 3, SCAN_OUTLIER = 4 };
 
 /* Opaque graph handle, owned by the library. */
 typedef struct scan_graph scan_graph;
@@ -66,6 +71,9 @@ typedef struct scan_opts {
                                    0 = grouped by the larger side, whose neighbours are
                                        staged in an LDS hash table (default);
                                    1 = one wave per edge, binary search in global memory */
+  int32_t hub_outlier;          /* 1: report SCAN_HUB / SCAN_OUTLIER instead of
+                                   SCAN_UNCLASSIFIED (one more pass over the edges,
+                                   Def 2.7 and Alg. 4); 0 (default): three roles */
   void* hip_stream;             /* hipStream_t to run on; NULL = a library-owned stream */
 } scan_opts;
 
@@ -104,6 +112,7 @@ int scan_graph_info(const scan_graph* g, int32_t* n, int64_t* nnz, int64_t* m, i
  * (problem statement of GPUSCAN++ Section 2.1; method of Algorithms 1-3).
  *   labels  host int32[n], caller-owned: cluster label (minimum core id) or -1
  *   roles   host uint8[n], caller-owned: SCAN_CORE, SCAN_BORDER or SCAN_UNCLASSIFIED
+ *           (SCAN_HUB / SCAN_OUTLIER in its place with opts.hub_outlier)
  * Requires 1 <= eps_num <= eps_den (0 < eps <= 1, Def 2.3) and mu >= 2 (Def 2.4).
  * Errors: SCAN_E_INVAL, SCAN_E_RANGE, SCAN_E_NOMEM, SCAN_E_DEVICE.
  */

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libscan_mi355x.so")
 
 SCAN_OK, SCAN_E_INVAL, SCAN_E_GRAPH, SCAN_E_RANGE, SCAN_E_NOMEM, SCAN_E_DEVICE = 0, -1, -2, -3, -4, -5
-SCAN_UNCLASSIFIED, SCAN_CORE, SCAN_BORDER = 0, 1, 2
+SCAN_UNCLASSIFIED, SCAN_CORE, SCAN_BORDER, SCAN_HUB, SCAN_OUTLIER = 0, 1, 2, 3, 4
 PHASES = ["init", "cores", "finalize", "hook", "merge", "flatten", "attach", "output"]
 NUM_PHASES = len(PHASES)
 NUM_BUCKETS = 7
@@ -53,6 +53,7 @@ class scan_opts(ctypes.Structure):
         ("pruning", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("strategy", ctypes.c_int32),
+        ("hub_outlier", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
     ]
 
@@ -169,9 +170,10 @@ def scan_opts_default() -> scan_opts:
 
 
 def make_opts(budget: int = 0, validate: bool = True, pruning: bool = True, timing: bool = False,
-              strategy: int = 0, stream: int | None = None) -> scan_opts:
+              strategy: int = 0, hub_outlier: bool = False, stream: int | None = None) -> scan_opts:
     o = scan_opts_default()
     o.strategy = int(strategy)
+    o.hub_outlier = int(bool(hub_outlier))
     o.device_budget_bytes = int(budget)
     o.validate = int(bool(validate))
     o.pruning = int(bool(pruning))

@@ -121,7 +121,12 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   mark(6);
   for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_ATTACH, k, A, cfg);
   mark(7);
-  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles, A.gid, gbase);
+  const int32_t split = g->opts.hub_outlier ? 1 : 0;
+  if (split) {  // Def 2.7; the cores pass's upper bounds are no longer needed
+    launch_fill_i32(s, g->d_upper, n, -1);
+    launch_hub_outlier_edges(s, m, g->d_edges, g->d_label, g->d_upper, g->d_role);
+  }
+  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles, split, A.gid, gbase);
   mark(8);
 }
 

@@ -706,8 +706,37 @@ __global__ void k_flatten(int32_t n, const uint8_t* role, int32_t* parent, int32
   label[u] = role[u] == ROLE_CORE ? uf_find(parent, (int32_t)u) : INT_MAX;
 }
 
+// Def 2.7 (the classification step, Alg. 4, done per edge): an edge with one
+// endpoint x in no cluster and the other in the cluster labelled L lets x
+// record the first L it meets in first[x]; meeting a different L makes x a hub.
+// A border's cluster is the label it was given.  first[] starts at -1.
+__global__ void k_hub_outlier(int64_t m, const int2* edges, const int32_t* label, int32_t* first,
+                              uint8_t* role) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < m; e += stride) {
+    const int2 uv = edges[e];
+    const int32_t lu = label[uv.x], lv = label[uv.y];
+    if ((lu == INT_MAX) == (lv == INT_MAX)) continue;
+    const int32_t x = (lu == INT_MAX) ? uv.x : uv.y;
+    const int32_t L = (lu == INT_MAX) ? lv : lu;
+    const int32_t seen = first[x];
+    if (seen == L) continue;
+    const int32_t old = (seen == -1) ? atomicCAS(first + x, -1, L) : seen;
+    if (old != -1 && old != L) role[x] = ROLE_HUB;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// Output roles: 1 core, 2 border, and for vertices in no cluster 0, or with
+// split set 3 (hub) / 4 (outlier).
 __global__ void k_output(int32_t n, const uint8_t* role, const int32_t* label, const int32_t* gid,
-                         const int32_t* gbase, int32_t* out_labels, uint8_t* out_roles) {
+                         const int32_t* gbase, int32_t* out_labels, uint8_t* out_roles, int32_t split) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   const int32_t l = label[u] - ((gid && label[u] != INT_MAX) ? gbase[gid[u]] : 0);  // batch: local ids
@@ -718,7 +747,7 @@ __global__ void k_output(int32_t n, const uint8_t* role, const int32_t* label, c
     out_roles[u] = 2;
     out_labels[u] = l;
   } else {
-    out_roles[u] = 0;
+    out_roles[u] = split ? (role[u] == ROLE_HUB ? 3 : 4) : 0;
     out_labels[u] = -1;
   }
 }
@@ -873,15 +902,26 @@ void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* pare
 }
 
 void launch_output(hipStream_t s, int32_t n, const uint8_t* role, const int32_t* label,
-                   int32_t* out_labels, uint8_t* out_roles, const int32_t* gid, const int32_t* gbase) {
-  if (n > 0) k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, gid, gbase, out_labels, out_roles);
+                   int32_t* out_labels, uint8_t* out_roles, int32_t split, const int32_t* gid,
+                   const int32_t* gbase) {
+  if (n > 0)
+    k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, gid, gbase, out_labels, out_roles, split);
+}
+
+void launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
+  if (n > 0) k_fill_i32<<<blocks_for(n, 256, 8192), 256, 0, s>>>(p, n, v);
+}
+
+void launch_hub_outlier_edges(hipStream_t s, int64_t m, const int2* edges, const int32_t* label, int32_t* first,
+                              uint8_t* role) {
+  if (m > 0) k_hub_outlier<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, label, first, role);
 }
 
 
 void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
                         const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
                         uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
-                        int32_t* out_labels, uint8_t* out_roles) {
+                        int32_t* out_labels, uint8_t* out_roles, int32_t split) {
   if (n <= 0) return;
   k_rt_init<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, lower, parent);
   if (m > 0) k_rt_edges<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, rp, ecount, p, q, state, lower);
@@ -889,7 +929,12 @@ void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, 
   if (m > 0) k_hook<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, state, role, parent);
   k_flatten<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, parent, label);
   if (m > 0) k_rt_attach<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, state, role, label);
-  k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, nullptr, nullptr, out_labels, out_roles);
+  if (split) {
+    k_fill_i32<<<blocks_for(n, 256, 8192), 256, 0, s>>>(lower, n, -1);  // counts are no longer needed
+    if (m > 0) k_hub_outlier<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, label, lower, role);
+  }
+  k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, nullptr, nullptr, out_labels, out_roles,
+                                                       split);
 }
 
 }  // namespace scan

@@ -306,7 +306,18 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
   mark(7);
-  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles);
+  const int32_t split = g->opts.hub_outlier ? 1 : 0;
+  if (split) {  // Def 2.7: one more pass over the edges, endpoints only
+    launch_fill_i32(s, g->d_upper, n, -1);
+    for (const PartChunk& C : P.chunks) {
+      const int64_t ne = C.end - C.begin;
+      HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
+              "edges H2D");
+      P.h2d_bytes += 8ull * (uint64_t)ne;
+      launch_hub_outlier_edges(s, ne, P.d_edges, g->d_label, g->d_upper, g->d_role);
+    }
+  }
+  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles, split);
   mark(8);
   HIP_TRY(hipGetLastError(), "kernel launch");
   unsigned long long stv[ST_COUNT];

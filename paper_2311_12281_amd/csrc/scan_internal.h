@@ -7,7 +7,8 @@
 namespace scan {
 
 // Per-vertex role during the run (Table 1 of the paper: ?, C, !C).
-enum : uint8_t { ROLE_UNK = 0, ROLE_CORE = 1, ROLE_NONCORE = 2 };
+enum : uint8_t { ROLE_UNK = 0, ROLE_CORE = 1, ROLE_NONCORE = 2,
+                 ROLE_HUB = 3 };  // ROLE_HUB: in no cluster, neighbours in two or more (Def 2.7)
 // Per-edge similarity state (Table 1: ?, S, !S).
 enum : uint8_t { SIM_UNK = 0, SIM_YES = 1, SIM_NO = 2 };
 
@@ -122,15 +123,20 @@ void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* 
 void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,
                  const uint8_t* role, int32_t* parent);
 void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* parent, int32_t* label);
+// split = 1: vertices in no cluster are output as hub (3) or outlier (4).
 void launch_output(hipStream_t s, int32_t n, const uint8_t* role, const int32_t* label,
-                   int32_t* out_labels, uint8_t* out_roles, const int32_t* gid = nullptr,
+                   int32_t* out_labels, uint8_t* out_roles, int32_t split, const int32_t* gid = nullptr,
                    const int32_t* gbase = nullptr);
+void launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+// Hub marking over m oriented edges (after attach): first[] must hold -1.
+void launch_hub_outlier_edges(hipStream_t s, int64_t m, const int2* edges, const int32_t* label, int32_t* first,
+                              uint8_t* role);
 
 // Serving: one query from cached per-edge closed counts (no intersections).
 void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
                         const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
                         uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
-                        int32_t* out_labels, uint8_t* out_roles);
+                        int32_t* out_labels, uint8_t* out_roles, int32_t split);
 
 // Layout (layout.hip)
 struct LayoutResult {

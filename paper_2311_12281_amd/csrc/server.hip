@@ -165,7 +165,7 @@ bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& 
   }
   launch_rethreshold(slot.stream, G->n, G->m, g->d_rp, g->d_edges, G->d_ecount, (uint64_t)p, (uint64_t)q,
                      r->mu, slot.d_lower, slot.d_role, slot.d_parent, slot.d_label, slot.d_state,
-                     slot.d_out_labels, slot.d_out_roles);
+                     slot.d_out_labels, slot.d_out_roles, S->opts.hub_outlier ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && G->n > 0)
     e = hipMemcpyAsync(slot.h_labels, slot.d_out_labels, 4 * (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
