@@ -563,11 +563,15 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         __syncthreads();
         for (int64_t k = w0 + tid; k < w1; k += kHubBlock) hub_insert(table, A.ci[bv + k]);
         __syncthreads();
-        // groups of kHubGroup lanes take chunks until none are left
+        // Groups of kHubGroup lanes take chunks until none are left.  The loop
+        // body branches on nothing that differs between the lanes of a group
+        // (the group's first lane alone adds through a select, not a branch):
+        // a branch on the lane index would let the compiler run the group's
+        // lanes around the loop separately, and the shuffles below need the
+        // whole group together.
         while (true) {
-          int32_t c = 0;
-          if (sub == 0) c = atomicAdd(&s_chunk, 1);
-          c = __shfl(c, gbase, 64);
+          const int32_t r = atomicAdd(&s_chunk, sub == 0 ? 1 : 0);
+          const int32_t c = __shfl(r, gbase, 64);
           if (c >= nchunks) break;
           int32_t lo = 0, hi2 = nbatch;  // survivor k: q_choff[k] <= c < q_choff[k + 1]
           while (hi2 - lo > 1) {
@@ -598,15 +602,14 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               hits += __popcll(__ballot(f) & gmask);
             }
           }
-          if (sub == 0) {
-            const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
-            const unsigned long long now = atomicAdd(&q_acc[k], add) + add;
-            if (!exact) {
-              const int32_t cnt = q_cnt[k] + (int32_t)(now & 0xffffffffu);
-              const int32_t done = q_pos[k] + (int32_t)(now >> 32);
-              if (cnt >= q_need[k]) q_st[k] = 2;
-              else if (cnt + (q_du[k] - done) < q_need[k]) q_st[k] = 3;
-            }
+          const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
+          const unsigned long long old = atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
+          if (!exact) {
+            const unsigned long long now = __shfl(old, gbase, 64) + add;
+            const int32_t cnt = q_cnt[k] + (int32_t)(now & 0xffffffffu);
+            const int32_t done = q_pos[k] + (int32_t)(now >> 32);
+            const uint8_t verdict = cnt >= q_need[k] ? 2 : (cnt + (q_du[k] - done) < q_need[k]) ? 3 : 0;
+            if (verdict) q_st[k] = verdict;  // the same value from every lane of the group
           }
         }
         __syncthreads();
