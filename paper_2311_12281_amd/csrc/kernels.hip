@@ -459,7 +459,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ int32_t q_pos[kHubBatch];    // elements of nbr(u) consumed before this window
   __shared__ int32_t q_end[kHubBatch];    // end of this window's part of nbr(u)
   __shared__ int32_t q_next[kHubBatch];   // next unread element of nbr(u) (INT_MAX at the end)
-  __shared__ int32_t q_choff[kHubBatch + 1];  // first chunk of each survivor in this window
+  __shared__ int32_t q_first[kHubBatch + 1];  // index of the survivor's first chunk among first chunks
+  __shared__ int32_t q_rest[kHubBatch + 1];   // index of its second chunk among the later chunks
   __shared__ uint8_t q_st[kHubBatch];     // 0 skipped, 1 active, 2 similar, 3 dissimilar
   __shared__ int32_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
@@ -536,8 +537,13 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         if (mn == INT_MAX) break;  // every survivor decided or fully read
         if (mn >= hi) continue;    // no survivor has an element in this window
         for (int k = tid; k < kHubSlots; k += kHubBlock) table[k] = -1;
-        // this window's part of every active survivor, cut into chunks of kHubChunk
-        int32_t nch = 0;
+        // This window's part of every active survivor, cut into chunks of
+        // kHubChunk.  Chunks are handed out first-chunk-of-every-survivor
+        // first, then the remaining chunks survivor by survivor, so that most
+        // verdicts (usually reached inside the first chunk) come before any
+        // group starts on a survivor's later chunks.  Per survivor, packed as
+        // (1 << 22) | (chunks - 1) so that one scan yields both offsets.
+        int32_t packed = 0;
         if (tid < nbatch) {
           q_acc[tid] = 0;
           if (q_st[tid] == 1 && q_next[tid] < hi) {
@@ -553,36 +559,47 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             } else {
               q_end[tid] = hi2;
             }
-            nch = (q_end[tid] - q_pos[tid] + kHubChunk - 1) / kHubChunk;
+            packed = (1 << 22) | ((q_end[tid] - q_pos[tid] - 1) / kHubChunk);
           }
         }
-        int32_t nchunks;
-        const int32_t choff = block_exclusive_scan(nch, wsum, &nchunks);
-        if (tid < nbatch) q_choff[tid] = choff;
-        if (tid == 0) q_choff[nbatch] = nchunks;
+        int32_t total;
+        const int32_t off = block_exclusive_scan(packed, wsum, &total);
+        const int32_t n_first = total >> 22, n_chunks = n_first + (total & ((1 << 22) - 1));
+        if (tid < nbatch) {
+          q_first[tid] = off >> 22;
+          q_rest[tid] = off & ((1 << 22) - 1);
+        }
+        if (tid == 0) {
+          q_first[nbatch] = n_first;
+          q_rest[nbatch] = total & ((1 << 22) - 1);
+        }
         __syncthreads();
         for (int64_t k = w0 + tid; k < w1; k += kHubBlock) hub_insert(table, A.ci[bv + k]);
         __syncthreads();
         // Groups of kHubGroup lanes take chunks until none are left.  The loop
         // body branches on nothing that differs between the lanes of a group
-        // (the group's first lane alone adds through a select, not a branch):
+        // (the group's first lane alone adds, through a select, not a branch):
         // a branch on the lane index would let the compiler run the group's
-        // lanes around the loop separately, and the shuffles below need the
-        // whole group together.
+        // lanes around the loop separately, and the shuffles need the whole
+        // group together.
         while (true) {
           const int32_t r = atomicAdd(&s_chunk, sub == 0 ? 1 : 0);
           const int32_t c = __shfl(r, gbase, 64);
-          if (c >= nchunks) break;
-          int32_t lo = 0, hi2 = nbatch;  // survivor k: q_choff[k] <= c < q_choff[k + 1]
+          if (c >= n_chunks) break;
+          const bool first = c < n_first;
+          const int32_t cc = first ? c : c - n_first;
+          const int32_t* pre = first ? q_first : q_rest;
+          int32_t lo = 0, hi2 = nbatch;  // survivor k: pre[k] <= cc < pre[k + 1]
           while (hi2 - lo > 1) {
             const int32_t mid = (lo + hi2) >> 1;
-            if (q_choff[mid] <= c) lo = mid;
+            if (pre[mid] <= cc) lo = mid;
             else hi2 = mid;
           }
           const int k = lo;
-          if (q_st[k] != 1) continue;  // decided by another chunk
+          if (q_st[k] != 1) continue;  // already decided
           const int32_t* Arow = A.ci + q_bu[k];
-          const int32_t cs = q_pos[k] + (c - q_choff[k]) * kHubChunk;
+          const int32_t base = q_pos[k], du = q_du[k], need = q_need[k], cnt0 = q_cnt[k];
+          const int32_t cs = first ? base : base + (1 + cc - pre[k]) * kHubChunk;
           const int32_t ce = (q_end[k] - cs < kHubChunk) ? q_end[k] : cs + kHubChunk;
           int32_t hits = 0;
           for (int32_t p = cs; p < ce; p += kStep) {
@@ -595,21 +612,35 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             }
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) q[j] = (x[j] >= 0) ? T4[hub_hash(x[j])] : make_int4(0, 0, 0, -1);
+            int32_t step_hits = 0;
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               bool f = x[j] >= 0 && bucket_has(q[j], x[j]);
               if (x[j] >= 0 && !f && q[j].w != -1) f = hub_probe_tail(T4, x[j]);
-              hits += __popcll(__ballot(f) & gmask);
+              step_hits += __popcll(__ballot(f) & gmask);
+            }
+            if (exact) {
+              hits += step_hits;
+            } else {
+              // fold this step into the survivor's running totals and stop as
+              // soon as its verdict is certain, or another group reached it
+              const int32_t n_step = (ce - p < kStep) ? ce - p : kStep;
+              const unsigned long long add = ((unsigned long long)n_step << 32) | (unsigned)step_hits;
+              const unsigned long long old = atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
+              const unsigned long long now = __shfl(old, gbase, 64) + add;
+              const int32_t cnt = cnt0 + (int32_t)(now & 0xffffffffu);
+              const int32_t done = base + (int32_t)(now >> 32);
+              const uint8_t verdict = cnt >= need ? 2 : (cnt + (du - done) < need) ? 3 : 0;
+              if (verdict) {
+                q_st[k] = verdict;  // the same value from every lane of the group
+                break;
+              }
+              if (q_st[k] != 1) break;
             }
           }
-          const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
-          const unsigned long long old = atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
-          if (!exact) {
-            const unsigned long long now = __shfl(old, gbase, 64) + add;
-            const int32_t cnt = q_cnt[k] + (int32_t)(now & 0xffffffffu);
-            const int32_t done = q_pos[k] + (int32_t)(now >> 32);
-            const uint8_t verdict = cnt >= q_need[k] ? 2 : (cnt + (q_du[k] - done) < q_need[k]) ? 3 : 0;
-            if (verdict) q_st[k] = verdict;  // the same value from every lane of the group
+          if (exact) {
+            const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
+            atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
           }
         }
         __syncthreads();

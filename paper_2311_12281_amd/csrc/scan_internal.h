@@ -63,8 +63,8 @@ constexpr int64_t kHubJobWork = 1 << 20;  // smaller-list elements per job (boun
 constexpr int kHubBlock = 512;     // threads per block of the LDS-hash kernel
 constexpr int kHubBatch = 256;     // survivors per table fill
 constexpr int kHubGroup = 16;      // lanes streaming one survivor
-constexpr int kHubUnroll = 4;      // elements per lane per step
-constexpr int kHubChunk = 256;     // elements of one survivor handed to a group at a time
+constexpr int kHubUnroll = 8;      // elements per lane per step
+constexpr int kHubChunk = 512;     // elements of one survivor handed to a group at a time
 constexpr int kHubLog2Slots = 14;  // LDS hash table: 16384 int32 slots = 64 KiB
 constexpr int kHubSlots = 1 << kHubLog2Slots;
 constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
