@@ -409,6 +409,9 @@ __device__ __forceinline__ void hub_insert(int32_t* table, int32_t x) {
   }
 }
 
+// Stands for "no element" in a probe: matches no slot (empty slots hold -1).
+constexpr int32_t kHubNone = -2;
+
 __device__ __forceinline__ bool bucket_has(int4 q, int32_t x) {
   return q.x == x || q.y == x || q.z == x || q.w == x;
 }
@@ -465,9 +468,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ int32_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
   __shared__ int32_t s_n, s_min, s_chunk;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int sub = lane & (kHubGroup - 1), gbase = lane & ~(kHubGroup - 1);
-  const uint64_t gmask = ((1ull << kHubGroup) - 1ull) << gbase;
+  const int tid = threadIdx.x;
+  const int sub = tid & (kHubGroup - 1);  // lane within its group
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
   const int4* T4 = reinterpret_cast<const int4*>(table);
   unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
@@ -583,8 +585,11 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         // lanes around the loop separately, and the shuffles need the whole
         // group together.
         while (true) {
-          const int32_t r = atomicAdd(&s_chunk, sub == 0 ? 1 : 0);
-          const int32_t c = __shfl(r, gbase, 64);
+          // every lane adds 1, so a group's lanes receive 16 consecutive
+          // values starting at a multiple of kHubGroup: value / kHubGroup is
+          // the group's chunk (a uniform addend keeps this a single atomic per
+          // wave and avoids any branch on the lane index)
+          const int32_t c = atomicAdd(&s_chunk, 1) / kHubGroup;
           if (c >= n_chunks) break;
           const bool first = c < n_first;
           const int32_t cc = first ? c : c - n_first;
@@ -601,33 +606,46 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           const int32_t base = q_pos[k], du = q_du[k], need = q_need[k], cnt0 = q_cnt[k];
           const int32_t cs = first ? base : base + (1 + cc - pre[k]) * kHubChunk;
           const int32_t ce = (q_end[k] - cs < kHubChunk) ? q_end[k] : cs + kHubChunk;
-          int32_t hits = 0;
+          // Each lane counts its own elements and hits and adds them to the
+          // survivor's running totals itself, so no step needs a reduction
+          // across the group.
+          uint32_t my_hits = 0, my_seen = 0;
           for (int32_t p = cs; p < ce; p += kStep) {
             int32_t x[kHubUnroll];
             int4 q[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               const int32_t i = p + j * kHubGroup + sub;
-              x[j] = (i < ce) ? Arow[i] : -1;
+              const int32_t y = Arow[i < ce ? i : ce - 1];  // in bounds, no branch
+              x[j] = (i < ce) ? y : kHubNone;
             }
 #pragma unroll
-            for (int j = 0; j < kHubUnroll; ++j) q[j] = (x[j] >= 0) ? T4[hub_hash(x[j])] : make_int4(0, 0, 0, -1);
-            int32_t step_hits = 0;
+            for (int j = 0; j < kHubUnroll; ++j) q[j] = T4[hub_hash(x[j])];
+            uint32_t step_hits = 0, step_seen = 0, tail = 0;
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              bool f = x[j] >= 0 && bucket_has(q[j], x[j]);
-              if (x[j] >= 0 && !f && q[j].w != -1) f = hub_probe_tail(T4, x[j]);
-              step_hits += __popcll(__ballot(f) & gmask);
+              const uint32_t xj = (uint32_t)x[j];
+              const uint32_t d = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
+                                     min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
+              step_hits += (d == 0u);
+              step_seen += (x[j] != kHubNone);
+              tail |= (uint32_t)((d != 0u) & (q[j].w != -1)) << j;  // bucket full: look further
+            }
+            if (__ballot(tail != 0u)) {  // rare (the table is at most half full)
+#pragma unroll
+              for (int j = 0; j < kHubUnroll; ++j)
+                if ((tail >> j) & 1u) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
             }
             if (exact) {
-              hits += step_hits;
+              my_hits += step_hits;
+              my_seen += step_seen;
             } else {
               // fold this step into the survivor's running totals and stop as
-              // soon as its verdict is certain, or another group reached it
-              const int32_t n_step = (ce - p < kStep) ? ce - p : kStep;
-              const unsigned long long add = ((unsigned long long)n_step << 32) | (unsigned)step_hits;
-              const unsigned long long old = atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
-              const unsigned long long now = __shfl(old, gbase, 64) + add;
+              // soon as its verdict is certain, or another group reached it;
+              // the totals are read back by one load for the whole group, so
+              // the verdict and the exit are the same on all of its lanes
+              atomicAdd(&q_acc[k], ((unsigned long long)step_seen << 32) | step_hits);
+              const unsigned long long now = q_acc[k];
               const int32_t cnt = cnt0 + (int32_t)(now & 0xffffffffu);
               const int32_t done = base + (int32_t)(now >> 32);
               const uint8_t verdict = cnt >= need ? 2 : (cnt + (du - done) < need) ? 3 : 0;
@@ -638,10 +656,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               if (q_st[k] != 1) break;
             }
           }
-          if (exact) {
-            const unsigned long long add = ((unsigned long long)(ce - cs) << 32) | (unsigned)hits;
-            atomicAdd(&q_acc[k], sub == 0 ? add : 0ull);
-          }
+          if (exact) atomicAdd(&q_acc[k], ((unsigned long long)my_seen << 32) | my_hits);
         }
         __syncthreads();
         if (tid < nbatch && q_st[tid] != 0 && q_next[tid] < hi) {
