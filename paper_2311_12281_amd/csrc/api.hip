@@ -277,6 +277,7 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     if (e != hipSuccess) { rc = fail_hip(e, what); goto error; } \
   } while (0)
   CTRY(hipGetDevice(&g->device), "hipGetDevice");
+  (void)hub_grid_blocks();
   if (g->opts.hip_stream) {
     g->stream = (hipStream_t)g->opts.hip_stream;
   } else {

@@ -483,24 +483,33 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
     if (job >= njobs) break;
     const HubJob J = jobs[job];
     const int64_t region = J.begin - A.e_begin;
-    // Phase A
-    for (int32_t base = 0; base < J.count; base += kHubBlock) {
-      const int32_t off = base + tid;
-      const int64_t e = J.begin + off;
-      EdgeView ev;
-      unsigned long long nb = 0;
-      classify<MODE>(A, e, off < J.count, ev, nb);
-      n_bound += nb;
-      if (ev.work == 2) {
-        apply<MODE>(A, e, ev, true, 0);
-      } else if (ev.work == 3) {
-        if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev, false, 0);
-      } else if (ev.work == 1) {
-        if (!exact && ev.need - 2 <= 0) {
-          ++n_eval;
-          apply<MODE>(A, e, ev, true, 0);
-        } else {
-          wl[region + atomicAdd(&s_n, 1)] = off;
+    // Phase A: each thread classifies kHubPerThread in-edges, all of their
+    // loads first (classification only reads), then acts on them.
+    for (int32_t base = 0; base < J.count; base += kHubBlock * kHubPerThread) {
+      EdgeView ev[kHubPerThread];
+      unsigned long long nb[kHubPerThread];
+#pragma unroll
+      for (int i = 0; i < kHubPerThread; ++i) {
+        const int32_t off = base + i * kHubBlock + tid;
+        nb[i] = 0;
+        classify<MODE>(A, J.begin + off, off < J.count, ev[i], nb[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < kHubPerThread; ++i) {
+        const int32_t off = base + i * kHubBlock + tid;
+        const int64_t e = J.begin + off;
+        n_bound += nb[i];
+        if (ev[i].work == 2) {
+          apply<MODE>(A, e, ev[i], true, 0);
+        } else if (ev[i].work == 3) {
+          if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev[i], false, 0);
+        } else if (ev[i].work == 1) {
+          if (!exact && ev[i].need - 2 <= 0) {
+            ++n_eval;
+            apply<MODE>(A, e, ev[i], true, 0);
+          } else {
+            wl[region + atomicAdd(&s_n, 1)] = off;
+          }
         }
       }
     }
@@ -576,7 +585,18 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           q_rest[nbatch] = total & ((1 << 22) - 1);
         }
         __syncthreads();
-        for (int64_t k = w0 + tid; k < w1; k += kHubBlock) hub_insert(table, A.ci[bv + k]);
+        // this window of nbr(v) into the table, kHubInsertBatch loads in flight per thread
+        for (int64_t k0 = w0 + tid; k0 < w1; k0 += (int64_t)kHubBlock * kHubInsertBatch) {
+          int32_t y[kHubInsertBatch];
+#pragma unroll
+          for (int i = 0; i < kHubInsertBatch; ++i) {
+            const int64_t k = k0 + (int64_t)i * kHubBlock;
+            y[i] = (k < w1) ? A.ci[bv + k] : kHubNone;
+          }
+#pragma unroll
+          for (int i = 0; i < kHubInsertBatch; ++i)
+            if (y[i] != kHubNone) hub_insert(table, y[i]);
+        }
         __syncthreads();
         // Groups of kHubGroup lanes take chunks until none are left.  The loop
         // body branches on nothing that differs between the lanes of a group
@@ -916,10 +936,25 @@ void launch_edges(hipStream_t s, int mode, int bucket, const EdgeArgs& a) {
   }
 }
 
+int hub_grid_blocks() {
+  static int n_cu = 0;  // compute units of the current device (the library drives one GPU)
+  if (n_cu == 0) {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      n_cu = cu;
+    else
+      n_cu = 256;
+  }
+  return n_cu;
+}
+
 void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
                 unsigned long long* counter, int32_t* worklist) {
   if (njobs <= 0) return;
-  const unsigned grid = blocks_for(njobs, 1, 1024);
+  // one resident block per compute unit (the table fills most of its LDS);
+  // blocks take jobs from the counter until none are left
+  const unsigned grid = blocks_for(njobs, 1, hub_grid_blocks());
   switch (mode) {
     case MODE_CORES: k_hub<MODE_CORES><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
     case MODE_MERGE: k_hub<MODE_MERGE><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;

@@ -60,12 +60,14 @@ __host__ __device__ inline uint32_t closed_needed(uint64_t p, uint64_t q, uint64
 // in-edges (u, v) of one larger side v, consecutive in the edge list.
 constexpr int kHubJobEdges = 4096; // in-edges per job
 constexpr int64_t kHubJobWork = 1 << 20;  // smaller-list elements per job (bound on probes)
-constexpr int kHubBlock = 512;     // threads per block of the LDS-hash kernel
-constexpr int kHubBatch = 256;     // survivors per table fill
+constexpr int kHubBlock = 1024;    // threads per block of the LDS-hash kernel (one block per CU)
+constexpr int kHubBatch = 512;     // survivors per table fill
+constexpr int kHubPerThread = kHubJobEdges / kHubBlock;  // in-edges classified per thread and round
+constexpr int kHubInsertBatch = 4; // table inserts per thread with their loads issued together
 constexpr int kHubGroup = 16;      // lanes streaming one survivor
 constexpr int kHubUnroll = 8;      // elements per lane per step
-constexpr int kHubChunk = 512;     // elements of one survivor handed to a group at a time
-constexpr int kHubLog2Slots = 14;  // LDS hash table: 16384 int32 slots = 64 KiB
+constexpr int kHubChunk = 2048;    // elements of one survivor handed to a group at a time
+constexpr int kHubLog2Slots = 15;  // LDS hash table: 32768 int32 slots = 128 KiB
 constexpr int kHubSlots = 1 << kHubLog2Slots;
 constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
 struct HubJob {
@@ -115,6 +117,9 @@ void launch_edges_lanes(hipStream_t s, int mode, int lanes, const EdgeArgs& a);
 // worklist holds one int32 per edge of the bucket.
 void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
                 unsigned long long* counter, int32_t* worklist);
+// Blocks of the LDS-hash kernel's grid (compute units of the device); queried
+// once, before any launch is captured into a HIP graph.
+int hub_grid_blocks();
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n);
 void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16);
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
