@@ -427,20 +427,20 @@ __device__ __noinline__ bool hub_probe_tail(const int4* T, int32_t x) {
   }
 }
 
-// Exclusive prefix sum of one int32 per thread over a block of kHubBlock
+// Exclusive prefix sum of one int64 per thread over a block of kHubBlock
 // threads; returns the sum of all values through *total.
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t x, int32_t* wsum, int32_t* total) {
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* wsum, int64_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int32_t incl = x;
+  int64_t incl = x;
   for (int d = 1; d < 64; d <<= 1) {
-    const int32_t y = __shfl_up(incl, d, 64);
+    const int64_t y = __shfl_up(incl, d, 64);
     if (lane >= d) incl += y;
   }
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  int32_t off = 0, tot = 0;
+  int64_t off = 0, tot = 0;
   for (int w = 0; w < kHubBlock / 64; ++w) {
-    const int32_t t = wsum[w];
+    const int64_t t = wsum[w];
     off += (w < wave) ? t : 0;
     tot += t;
   }
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ int32_t q_first[kHubBatch + 1];  // index of the survivor's first chunk among first chunks
   __shared__ int32_t q_rest[kHubBatch + 1];   // index of its second chunk among the later chunks
   __shared__ uint8_t q_st[kHubBatch];     // 0 skipped, 1 active, 2 similar, 3 dissimilar
-  __shared__ int32_t wsum[kHubBlock / 64];
+  __shared__ int64_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
   __shared__ int32_t s_n, s_min, s_chunk;
   const int tid = threadIdx.x;
@@ -553,8 +553,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         // first, then the remaining chunks survivor by survivor, so that most
         // verdicts (usually reached inside the first chunk) come before any
         // group starts on a survivor's later chunks.  Per survivor, packed as
-        // (1 << 22) | (chunks - 1) so that one scan yields both offsets.
-        int32_t packed = 0;
+        // (1 << 32) | (chunks - 1) so that one scan yields both offsets.
+        int64_t packed = 0;
         if (tid < nbatch) {
           q_acc[tid] = 0;
           if (q_st[tid] == 1 && q_next[tid] < hi) {
@@ -570,19 +570,21 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             } else {
               q_end[tid] = hi2;
             }
-            packed = (1 << 22) | ((q_end[tid] - q_pos[tid] - 1) / kHubChunk);
+            packed = (1ll << 32) | (int64_t)((q_end[tid] - q_pos[tid] - 1) / kHubChunk);
           }
         }
-        int32_t total;
-        const int32_t off = block_exclusive_scan(packed, wsum, &total);
-        const int32_t n_first = total >> 22, n_chunks = n_first + (total & ((1 << 22) - 1));
+        int64_t total;
+        const int64_t off = block_exclusive_scan(packed, wsum, &total);
+        const int32_t n_first = (int32_t)(total >> 32);
+        const int32_t n_rest = (int32_t)(total & 0xffffffffll);
+        const int32_t n_chunks = n_first + n_rest;
         if (tid < nbatch) {
-          q_first[tid] = off >> 22;
-          q_rest[tid] = off & ((1 << 22) - 1);
+          q_first[tid] = (int32_t)(off >> 32);
+          q_rest[tid] = (int32_t)(off & 0xffffffffll);
         }
         if (tid == 0) {
           q_first[nbatch] = n_first;
-          q_rest[nbatch] = total & ((1 << 22) - 1);
+          q_rest[nbatch] = n_rest;
         }
         __syncthreads();
         // this window of nbr(v) into the table, kHubInsertBatch loads in flight per thread

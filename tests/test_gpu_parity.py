@@ -283,6 +283,15 @@ def test_windowed_hub():
     check_graph(g, [((1, 10), 2), ((1, 5), 3), ((1, 20), 5), ((1, 100), 2)], "windowed-hub")
 
 
+def test_full_survivor_batch():
+    """More heavy in-edges of one hub than a table fill takes (every one of them
+    intersected, all in one window), so a fill holds a full batch of active
+    survivors."""
+    g = windowed_hub_graph(seed=9, hub_deg=3000, heavy=1400, extra=120)
+    check_graph(g, [((1, 10), 2), ((1, 5), 3), ((1, 4), 5), ((1, 1), 2)], "full-survivor-batch")
+    check_graph(g, [((1, 5), 3)], "full-survivor-batch-exhaustive", counts=False, pruning=False)
+
+
 @pytest.mark.parametrize("name,gen", [
     ("rmat16", lambda: gg.rmat(16, 16, seed=2)),
     ("windowed-hub", windowed_hub_graph),
