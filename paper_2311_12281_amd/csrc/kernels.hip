@@ -204,6 +204,30 @@ __device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, Edge
   return true;
 }
 
+// Cores pass, effect of a decided edge in two halves, so that a thread can
+// have the counter updates of several edges in flight before it needs their
+// results: the bound moved on both endpoints (lower on a similar edge, upper on
+// a dissimilar one; both atomics issued back to back, values before the update
+// returned), then the roles those values settle (Lemma 4.1).
+__device__ __forceinline__ void cores_count(const EdgeArgs& A, const EdgeView& ev, bool sim, int32_t& cu,
+                                            int32_t& cv) {
+  int32_t* c = sim ? A.lower : A.upper;
+  const int32_t d = sim ? 1 : -1;
+  cu = atomicAdd(c + ev.u, d);
+  cv = atomicAdd(c + ev.v, d);
+}
+
+__device__ __forceinline__ void cores_roles(const EdgeArgs& A, const EdgeView& ev, bool sim, int32_t cu,
+                                            int32_t cv) {
+  if (sim) {
+    if (cu + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
+    if (cv + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
+  } else {
+    if (cu - 1 < ev.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
+    if (cv - 1 < ev.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
+  }
+}
+
 // Effect of a decided edge; executed by one lane.
 template <int MODE>
 __device__ __forceinline__ void apply(const EdgeArgs& A, int64_t e, const EdgeView& ev, bool sim,
@@ -219,14 +243,10 @@ __device__ __forceinline__ void apply(const EdgeArgs& A, int64_t e, const EdgeVi
     return;
   }
   if (MODE == MODE_CORES) {
+    int32_t cu, cv;
+    cores_count(A, ev, sim, cu, cv);
     A.state[e] = sim ? SIM_YES : SIM_NO;
-    if (sim) {
-      if (atomicAdd(A.lower + ev.u, 1) + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
-      if (atomicAdd(A.lower + ev.v, 1) + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
-    } else {
-      if (atomicSub(A.upper + ev.u, 1) - 1 < ev.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
-      if (atomicSub(A.upper + ev.v, 1) - 1 < ev.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
-    }
+    cores_roles(A, ev, sim, cu, cv);
   } else if (MODE == MODE_MERGE) {
     A.state[e] = sim ? SIM_YES : SIM_NO;
     if (sim) uf_union(A.parent, ev.u, ev.v);
@@ -494,23 +514,38 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         nb[i] = 0;
         classify<MODE>(A, J.begin + off, off < J.count, ev[i], nb[i]);
       }
+      // edges decided without an intersection: dissimilar by the degree
+      // bound (3), similar because two closed neighbours suffice, or already
+      // known similar (2, attach pass)
+      bool act[kHubPerThread], sim[kHubPerThread];
+#pragma unroll
+      for (int i = 0; i < kHubPerThread; ++i) {
+        n_bound += nb[i];
+        const bool trivial = ev[i].work == 1 && !exact && ev[i].need - 2 <= 0;
+        act[i] = ev[i].work == 2 || (ev[i].work == 3 && MODE != MODE_ATTACH) || trivial;
+        sim[i] = ev[i].work == 2 || trivial;
+        n_eval += trivial ? 1 : 0;
+      }
+      if (MODE == MODE_CORES) {
+        int32_t cu[kHubPerThread], cv[kHubPerThread];
+#pragma unroll
+        for (int i = 0; i < kHubPerThread; ++i)
+          if (act[i]) cores_count(A, ev[i], sim[i], cu[i], cv[i]);
+#pragma unroll
+        for (int i = 0; i < kHubPerThread; ++i) {
+          if (!act[i]) continue;
+          A.state[J.begin + base + i * kHubBlock + tid] = sim[i] ? SIM_YES : SIM_NO;
+          cores_roles(A, ev[i], sim[i], cu[i], cv[i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kHubPerThread; ++i)
+          if (act[i]) apply<MODE>(A, J.begin + base + i * kHubBlock + tid, ev[i], sim[i], 0);
+      }
 #pragma unroll
       for (int i = 0; i < kHubPerThread; ++i) {
         const int32_t off = base + i * kHubBlock + tid;
-        const int64_t e = J.begin + off;
-        n_bound += nb[i];
-        if (ev[i].work == 2) {
-          apply<MODE>(A, e, ev[i], true, 0);
-        } else if (ev[i].work == 3) {
-          if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev[i], false, 0);
-        } else if (ev[i].work == 1) {
-          if (!exact && ev[i].need - 2 <= 0) {
-            ++n_eval;
-            apply<MODE>(A, e, ev[i], true, 0);
-          } else {
-            wl[region + atomicAdd(&s_n, 1)] = off;
-          }
-        }
+        if (ev[i].work == 1 && !act[i]) wl[region + atomicAdd(&s_n, 1)] = off;
       }
     }
     __syncthreads();
