@@ -59,7 +59,7 @@ __host__ __device__ inline uint32_t closed_needed(uint64_t p, uint64_t q, uint64
 // LDS-hash kernel of the last bucket (d_u > 64): one job = up to kHubJobEdges
 // in-edges (u, v) of one larger side v, consecutive in the edge list.
 constexpr int kHubJobEdges = 4096; // in-edges per job
-constexpr int64_t kHubJobWork = 1 << 20;  // smaller-list elements per job (bound on probes)
+constexpr int64_t kHubJobWork = 1 << 24;  // smaller-list elements per job (bound on probes)
 constexpr int kHubBlock = 1024;    // threads per block of the LDS-hash kernel (one block per CU)
 constexpr int kHubBatch = 512;     // survivors per table fill
 constexpr int kHubPerThread = kHubJobEdges / kHubBlock;  // in-edges classified per thread and round
