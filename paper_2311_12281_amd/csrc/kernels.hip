@@ -407,26 +407,47 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 //            element in LDS, so nbr(u_i) is read once in total and windows
 //            below every survivor's next element are not built at all.  A
 //            survivor stops as soon as its verdict is certain.
-// Bucketed open addressing: kHubSlots int32 slots viewed as buckets of 4;
-// an element goes to the first free slot of bucket hash(x), or of the next
-// buckets in turn if that one is full.  Slots fill in order within a bucket,
-// so a bucket with a free last slot has never overflowed: a probe reads one
-// bucket (a single 16-byte LDS load) and continues only when it is full.
-constexpr int kHubBuckets = kHubSlots / 4;
-__device__ __forceinline__ uint32_t hub_hash(int32_t x) {
-  return ((uint32_t)x * 0x9E3779B1u) >> (32 - (kHubLog2Slots - 2));
+// LDS hash set: kHubSlots int32 slots viewed as buckets of 4 (one 16-byte
+// LDS load each).  Two-choice placement: every element has two buckets, both
+// derived from one multiplicative hash, and goes to the emptier one; only when
+// both are full does it go on to the first bucket after its second one that
+// has room.  A probe reads both buckets at once; it has to look further only
+// when both are full and neither holds the element, which two-choice placement
+// at half load makes rare.  Slots of a bucket fill in order (each insert takes
+// its first free slot), so a bucket is full exactly when its last slot is set,
+// and slots are never freed while a table is in use: a bucket that is not full
+// at probe time was not full when any later element was placed.
+constexpr int kHubBucketBits = kHubLog2Slots - 2;
+constexpr int kHubBuckets = 1 << kHubBucketBits;
+static_assert(2 * kHubBucketBits <= 32, "both bucket indices come from one 32-bit product");
+__device__ __forceinline__ void hub_buckets(int32_t x, uint32_t& b1, uint32_t& b2) {
+  const uint32_t h = (uint32_t)x * 0x9E3779B1u;
+  b1 = h >> (32 - kHubBucketBits);
+  b2 = ((h >> (32 - 2 * kHubBucketBits)) ^ h) & (kHubBuckets - 1);
+}
+
+__device__ __forceinline__ int bucket_free(int4 q) {
+  return (q.x == -1) + (q.y == -1) + (q.z == -1) + (q.w == -1);
+}
+
+__device__ __forceinline__ bool bucket_put(int32_t* table, uint32_t b, int32_t x) {
+  int32_t* slot = table + 4 * b;
+  if (atomicCAS(slot + 0, -1, x) == -1) return true;
+  if (atomicCAS(slot + 1, -1, x) == -1) return true;
+  if (atomicCAS(slot + 2, -1, x) == -1) return true;
+  return atomicCAS(slot + 3, -1, x) == -1;
 }
 
 __device__ __forceinline__ void hub_insert(int32_t* table, int32_t x) {
-  uint32_t b = hub_hash(x);
-  while (true) {
-    int32_t* slot = table + 4 * b;
-    if (atomicCAS(slot + 0, -1, x) == -1) return;
-    if (atomicCAS(slot + 1, -1, x) == -1) return;
-    if (atomicCAS(slot + 2, -1, x) == -1) return;
-    if (atomicCAS(slot + 3, -1, x) == -1) return;
-    b = (b + 1) & (kHubBuckets - 1);
-  }
+  uint32_t b1, b2;
+  hub_buckets(x, b1, b2);
+  const int4* T = reinterpret_cast<const int4*>(table);
+  // the loads only steer the choice; the CAS loops decide where x lands
+  const bool second_first = bucket_free(T[b2]) > bucket_free(T[b1]);
+  if (bucket_put(table, second_first ? b2 : b1, x)) return;
+  if (bucket_put(table, second_first ? b1 : b2, x)) return;
+  uint32_t b = (b2 + 1) & (kHubBuckets - 1);
+  while (!bucket_put(table, b, x)) b = (b + 1) & (kHubBuckets - 1);
 }
 
 // Stands for "no element" in a probe: matches no slot (empty slots hold -1).
@@ -436,9 +457,11 @@ __device__ __forceinline__ bool bucket_has(int4 q, int32_t x) {
   return q.x == x || q.y == x || q.z == x || q.w == x;
 }
 
-// Rest of a probe whose first bucket was full.
+// Rest of a probe whose two buckets were both full.
 __device__ __noinline__ bool hub_probe_tail(const int4* T, int32_t x) {
-  uint32_t b = (hub_hash(x) + 1) & (kHubBuckets - 1);
+  uint32_t b1, b2;
+  hub_buckets(x, b1, b2);
+  uint32_t b = (b2 + 1) & (kHubBuckets - 1);
   while (true) {
     const int4 q = T[b];
     if (bucket_has(q, x)) return true;
@@ -669,7 +692,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           uint32_t my_hits = 0, my_seen = 0;
           for (int32_t p = cs; p < ce; p += kStep) {
             int32_t x[kHubUnroll];
-            int4 q[kHubUnroll];
+            int4 q[kHubUnroll], r[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               const int32_t i = p + j * kHubGroup + sub;
@@ -677,18 +700,26 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               x[j] = (i < ce) ? y : kHubNone;
             }
 #pragma unroll
-            for (int j = 0; j < kHubUnroll; ++j) q[j] = T4[hub_hash(x[j])];
+            for (int j = 0; j < kHubUnroll; ++j) {
+              uint32_t b1, b2;
+              hub_buckets(x[j], b1, b2);
+              q[j] = T4[b1];
+              r[j] = T4[b2];
+            }
             uint32_t step_hits = 0, step_seen = 0, tail = 0;
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               const uint32_t xj = (uint32_t)x[j];
-              const uint32_t d = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
-                                     min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
+              const uint32_t d = min(min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
+                                         min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj)),
+                                     min(min((uint32_t)r[j].x ^ xj, (uint32_t)r[j].y ^ xj),
+                                         min((uint32_t)r[j].z ^ xj, (uint32_t)r[j].w ^ xj)));
               step_hits += (d == 0u);
               step_seen += (x[j] != kHubNone);
-              tail |= (uint32_t)((d != 0u) & (q[j].w != -1)) << j;  // bucket full: look further
+              // both buckets full and x in neither: it may sit further on
+              tail |= (uint32_t)((d != 0u) & (q[j].w != -1) & (r[j].w != -1)) << j;
             }
-            if (__ballot(tail != 0u)) {  // rare (the table is at most half full)
+            if (__ballot(tail != 0u)) {  // rare: both of an element's buckets full
 #pragma unroll
               for (int j = 0; j < kHubUnroll; ++j)
                 if ((tail >> j) & 1u) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
