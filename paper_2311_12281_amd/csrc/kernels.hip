@@ -325,8 +325,13 @@ __device__ __forceinline__ T shfl_t(T x, int src) {
 // per group of G lanes (the edge's fields are broadcast from the lane that
 // classified it).  Buckets 0-4 use G >= d_s (one tile); G = 64 also serves the
 // last bucket when it runs without the LDS-hash kernel.
-template <int MODE, int G>
+// STAGE (bucket 5, G = 64: both sides above 64 neighbours, the larger at most
+// kHubMinDegree): the wave first copies nbr(v) into its own LDS slot, so the
+// binary searches run in LDS instead of global memory.
+template <int MODE, int G, bool STAGE = false>
 __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
+  static_assert(!STAGE || G == 64, "staging is per wave");
+  __shared__ int32_t stage[STAGE ? (kBlock / 64) * kHubMinDegree : 1];
   constexpr int kGroups = 64 / G;
   const int lane = threadIdx.x & 63;
   const int grp = lane / G, sub = lane & (G - 1), gbase = lane & ~(G - 1);
@@ -376,8 +381,21 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
       if (act) {
         int32_t cnt;
         int64_t consumed;
-        const int verdict = group_intersect<G>(A.ci + w.bu, w.du, A.ci + w.bv, w.dv, w.need - 2, exact,
-                                               sub, gbase, gmask, cnt, consumed);
+        int verdict;
+        if (STAGE && w.dv <= kHubMinDegree) {  // uniform over the wave (G = 64)
+          int32_t* S = stage + (threadIdx.x >> 6) * kHubMinDegree;
+          // the wave's reads of the previous edge's copy come first
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          for (int64_t i = lane; i < w.dv; i += 64) S[i] = A.ci[w.bv + i];
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          verdict = group_intersect<G>(A.ci + w.bu, w.du, S, w.dv, w.need - 2, exact, sub, gbase, gmask,
+                                       cnt, consumed);
+        } else {
+          verdict = group_intersect<G>(A.ci + w.bu, w.du, A.ci + w.bv, w.dv, w.need - 2, exact, sub, gbase,
+                                       gmask, cnt, consumed);
+        }
         if (sub == 0) {
           ++n_eval;
           n_probe += (unsigned long long)consumed;
@@ -957,6 +975,7 @@ void launch_edges_mode(hipStream_t s, int bucket, const EdgeArgs& a) {
     case 1: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
     case 2: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
     case 3: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
+    case 5: k_group<MODE, 64, true><<<grid, kBlock, 0, s>>>(a); break;
     default: k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a); break;
   }
 }
@@ -982,7 +1001,10 @@ void launch_edges_width(hipStream_t s, int lanes, const EdgeArgs& a) {
     case 8: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
     case 16: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
     case 32: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
-    default: k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a); break;
+    default:
+      if (a.bucket == 5) k_group<MODE, 64, true><<<grid, kBlock, 0, s>>>(a);
+      else k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a);
+      break;
   }
 }
 
