@@ -708,34 +708,50 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           // survivor's running totals itself, so no step needs a reduction
           // across the group.
           uint32_t my_hits = 0, my_seen = 0;
+          // elements of the next step are loaded while this one is probed
+          // (indices clamped into the chunk: every load is in bounds)
+          int32_t xn[kHubUnroll];
+#pragma unroll
+          for (int j = 0; j < kHubUnroll; ++j) {
+            const int32_t i = cs + j * kHubGroup + sub;
+            xn[j] = Arow[i < ce ? i : ce - 1];
+          }
           for (int32_t p = cs; p < ce; p += kStep) {
             int32_t x[kHubUnroll];
-            int4 q[kHubUnroll], r[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              const int32_t i = p + j * kHubGroup + sub;
-              const int32_t y = Arow[i < ce ? i : ce - 1];  // in bounds, no branch
-              x[j] = (i < ce) ? y : kHubNone;
+              x[j] = (p + j * kHubGroup + sub < ce) ? xn[j] : kHubNone;
+              const int32_t i = p + kStep + j * kHubGroup + sub;
+              xn[j] = Arow[i < ce ? i : ce - 1];
             }
+            // first buckets of all elements, then second buckets, in the same registers
+            int4 q[kHubUnroll];
+            uint32_t d[kHubUnroll], b2[kHubUnroll], full = 0;
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              uint32_t b1, b2;
-              hub_buckets(x[j], b1, b2);
+              uint32_t b1;
+              hub_buckets(x[j], b1, b2[j]);
               q[j] = T4[b1];
-              r[j] = T4[b2];
             }
+#pragma unroll
+            for (int j = 0; j < kHubUnroll; ++j) {
+              const uint32_t xj = (uint32_t)x[j];
+              d[j] = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
+                         min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
+              full |= (uint32_t)(q[j].w != -1) << j;
+            }
+#pragma unroll
+            for (int j = 0; j < kHubUnroll; ++j) q[j] = T4[b2[j]];
             uint32_t step_hits = 0, step_seen = 0, tail = 0;
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               const uint32_t xj = (uint32_t)x[j];
-              const uint32_t d = min(min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
-                                         min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj)),
-                                     min(min((uint32_t)r[j].x ^ xj, (uint32_t)r[j].y ^ xj),
-                                         min((uint32_t)r[j].z ^ xj, (uint32_t)r[j].w ^ xj)));
-              step_hits += (d == 0u);
+              const uint32_t dj = min(d[j], min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
+                                                min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj)));
+              step_hits += (dj == 0u);
               step_seen += (x[j] != kHubNone);
               // both buckets full and x in neither: it may sit further on
-              tail |= (uint32_t)((d != 0u) & (q[j].w != -1) & (r[j].w != -1)) << j;
+              tail |= (uint32_t)((dj != 0u) & ((full >> j) & 1u) & (q[j].w != -1)) << j;
             }
             if (__ballot(tail != 0u)) {  // rare: both of an element's buckets full
 #pragma unroll
