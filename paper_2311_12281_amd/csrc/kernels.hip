@@ -104,6 +104,8 @@ struct EdgeView {
   int32_t core_label; // ATTACH
   int32_t mu;         // the edge's graph's mu
   uint8_t work;       // 1: run the intersection
+  uint8_t open_u, open_v;  // cores pass: the endpoint's role was still unknown when read, so
+                           // its bounds still matter (a known role never changes again)
 };
 
 // eps = p/q and mu of the graph holding vertex x (one graph, or a batch of
@@ -126,6 +128,7 @@ template <int MODE>
 __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool active, EdgeView& ev,
                                          unsigned long long& n_bound) {
   ev = EdgeView{};
+  ev.open_u = ev.open_v = 1;
   if (!active) return;
   const int2 uv = A.edges[e];
   ev.u = uv.x;
@@ -146,6 +149,8 @@ __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool acti
     if (A.pruning) {
       const uint8_t ru = ld_u8(A.role + ev.u), rv = ld_u8(A.role + ev.v);
       if (ru != ROLE_UNK && rv != ROLE_UNK) return;  // Alg. 2: both roles known, defer
+      ev.open_u = ru == ROLE_UNK;
+      ev.open_v = rv == ROLE_UNK;
     }
   } else if (MODE == MODE_MERGE) {
     if (A.state[e] != SIM_UNK) return;
@@ -189,12 +194,18 @@ __device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, Edge
   ev.bv = row_start(A, ev.v);
   ev.need = 0;
   ev.work = 1;
+  ev.open_u = ev.open_v = 1;
   if (MODE == MODE_COUNTS) return true;
   uint64_t p, q;
   graph_params(A, ev.u, p, q, ev.mu);
   ev.need = (int32_t)closed_needed(p, q, (uint64_t)ev.du + 1, (uint64_t)ev.dv + 1);
   if (MODE == MODE_CORES) {
-    if (A.pruning && ld_u8(A.role + ev.u) != ROLE_UNK && ld_u8(A.role + ev.v) != ROLE_UNK) return false;
+    if (A.pruning) {
+      const uint8_t ru = ld_u8(A.role + ev.u), rv = ld_u8(A.role + ev.v);
+      if (ru != ROLE_UNK && rv != ROLE_UNK) return false;
+      ev.open_u = ru == ROLE_UNK;
+      ev.open_v = rv == ROLE_UNK;
+    }
   } else if (MODE == MODE_ATTACH) {
     const bool cu = ld_u8(A.role + ev.u) == ROLE_CORE;
     ev.core_side = cu ? ev.u : ev.v;
@@ -209,22 +220,24 @@ __device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, Edge
 // results: the bound moved on both endpoints (lower on a similar edge, upper on
 // a dissimilar one; both atomics issued back to back, values before the update
 // returned), then the roles those values settle (Lemma 4.1).
-__device__ __forceinline__ void cores_count(const EdgeArgs& A, const EdgeView& ev, bool sim, int32_t& cu,
-                                            int32_t& cv) {
+// Only endpoints whose role was unknown are updated (do_u, do_v): a known role
+// never changes, and the final count is read only for roles still unknown.
+__device__ __forceinline__ void cores_count(const EdgeArgs& A, const EdgeView& ev, bool sim, bool do_u,
+                                            bool do_v, int32_t& cu, int32_t& cv) {
   int32_t* c = sim ? A.lower : A.upper;
   const int32_t d = sim ? 1 : -1;
-  cu = atomicAdd(c + ev.u, d);
-  cv = atomicAdd(c + ev.v, d);
+  cu = do_u ? atomicAdd(c + ev.u, d) : 0;
+  cv = do_v ? atomicAdd(c + ev.v, d) : 0;
 }
 
-__device__ __forceinline__ void cores_roles(const EdgeArgs& A, const EdgeView& ev, bool sim, int32_t cu,
-                                            int32_t cv) {
+__device__ __forceinline__ void cores_roles(const EdgeArgs& A, const EdgeView& ev, bool sim, bool do_u,
+                                            bool do_v, int32_t cu, int32_t cv) {
   if (sim) {
-    if (cu + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
-    if (cv + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
+    if (do_u && cu + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
+    if (do_v && cv + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
   } else {
-    if (cu - 1 < ev.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
-    if (cv - 1 < ev.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
+    if (do_u && cu - 1 < ev.mu) st_u8(A.role + ev.u, ROLE_NONCORE);
+    if (do_v && cv - 1 < ev.mu) st_u8(A.role + ev.v, ROLE_NONCORE);
   }
 }
 
@@ -244,9 +257,9 @@ __device__ __forceinline__ void apply(const EdgeArgs& A, int64_t e, const EdgeVi
   }
   if (MODE == MODE_CORES) {
     int32_t cu, cv;
-    cores_count(A, ev, sim, cu, cv);
+    cores_count(A, ev, sim, ev.open_u, ev.open_v, cu, cv);
     A.state[e] = sim ? SIM_YES : SIM_NO;
-    cores_roles(A, ev, sim, cu, cv);
+    cores_roles(A, ev, sim, ev.open_u, ev.open_v, cu, cv);
   } else if (MODE == MODE_MERGE) {
     A.state[e] = sim ? SIM_YES : SIM_NO;
     if (sim) uf_union(A.parent, ev.u, ev.v);
@@ -377,6 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
       w.other = shfl_t(ev.other, src);
       w.core_label = shfl_t(ev.core_label, src);
       w.mu = shfl_t(ev.mu, src);
+      w.open_u = (uint8_t)shfl_t((int32_t)ev.open_u, src);
+      w.open_v = (uint8_t)shfl_t((int32_t)ev.open_v, src);
       const int64_t we = shfl_t(e, src);
       if (act) {
         int32_t cnt;
@@ -529,6 +544,10 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ int64_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
   __shared__ int32_t s_n, s_min, s_chunk;
+  // cores pass: similar / dissimilar verdicts of this job's edges on the common
+  // larger side v, applied to v's bounds once per job (all of a job's edges
+  // would otherwise update the same two counters one by one)
+  __shared__ int32_t s_vsim, s_vdis;
   const int tid = threadIdx.x;
   const int sub = tid & (kHubGroup - 1);  // lane within its group
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
@@ -538,6 +557,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
     if (tid == 0) {
       s_job = (int64_t)atomicAdd(counter, 1ull);
       s_n = 0;
+      s_vsim = 0;
+      s_vdis = 0;
     }
     __syncthreads();
     const int64_t job = s_job;
@@ -568,16 +589,22 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         n_eval += trivial ? 1 : 0;
       }
       if (MODE == MODE_CORES) {
-        int32_t cu[kHubPerThread], cv[kHubPerThread];
+        int32_t cu[kHubPerThread], cv[kHubPerThread], vsim = 0, vdis = 0;
 #pragma unroll
         for (int i = 0; i < kHubPerThread; ++i)
-          if (act[i]) cores_count(A, ev[i], sim[i], cu[i], cv[i]);
+          if (act[i]) cores_count(A, ev[i], sim[i], ev[i].open_u, false, cu[i], cv[i]);
 #pragma unroll
         for (int i = 0; i < kHubPerThread; ++i) {
           if (!act[i]) continue;
           A.state[J.begin + base + i * kHubBlock + tid] = sim[i] ? SIM_YES : SIM_NO;
-          cores_roles(A, ev[i], sim[i], cu[i], cv[i]);
+          cores_roles(A, ev[i], sim[i], ev[i].open_u, false, cu[i], cv[i]);
+          if (ev[i].open_v) {
+            vsim += sim[i] ? 1 : 0;
+            vdis += sim[i] ? 0 : 1;
+          }
         }
+        if (vsim) atomicAdd(&s_vsim, vsim);
+        if (vdis) atomicAdd(&s_vdis, vdis);
       } else {
 #pragma unroll
         for (int i = 0; i < kHubPerThread; ++i)
@@ -804,9 +831,24 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         ++n_eval;
         n_probe += (unsigned long long)q_pos[tid];
         const bool sim = st == 2 ? true : st == 3 ? false : (cnt + 2 >= ev.need);
-        apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : sim, cnt + 2);
+        if (MODE == MODE_CORES) {
+          int32_t cu, cv;
+          cores_count(A, ev, sim, ev.open_u, false, cu, cv);
+          A.state[e] = sim ? SIM_YES : SIM_NO;
+          cores_roles(A, ev, sim, ev.open_u, false, cu, cv);
+          if (ev.open_v) atomicAdd(sim ? &s_vsim : &s_vdis, 1);
+        } else {
+          apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : sim, cnt + 2);
+        }
       }
       __syncthreads();
+    }
+    if (MODE == MODE_CORES && tid == 0 && (s_vsim | s_vdis)) {
+      uint64_t gp, gq;
+      int32_t vmu;
+      graph_params(A, J.v, gp, gq, vmu);
+      if (s_vsim && atomicAdd(A.lower + J.v, s_vsim) + s_vsim >= vmu) st_u8(A.role + J.v, ROLE_CORE);
+      if (s_vdis && atomicSub(A.upper + J.v, s_vdis) - s_vdis < vmu) st_u8(A.role + J.v, ROLE_NONCORE);
     }
     __syncthreads();  // every thread is done with this job's shared values
   }
