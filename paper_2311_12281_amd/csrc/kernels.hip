@@ -222,16 +222,27 @@ __device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, Edge
 // returned), then the roles those values settle (Lemma 4.1).
 // Only endpoints whose role was unknown are updated (do_u, do_v): a known role
 // never changes, and the final count is read only for roles still unknown.
+// The upper bound is kept only for degrees up to kUpperMaxDegree: it serves
+// just to mark a vertex non-core early (Lemma 4.1), which for a vertex of
+// higher degree happens only after nearly all of its edges were tested, while
+// every one of its edges would update the same counter.  Such a vertex keeps
+// role ? and is settled from its exact lower bound at the end of the pass.
+constexpr int64_t kUpperMaxDegree = 256;
+static_assert(kUpperMaxDegree < kHubMinDegree, "the LDS-hash kernel keeps no upper bound for its larger side");
 __device__ __forceinline__ void cores_count(const EdgeArgs& A, const EdgeView& ev, bool sim, bool do_u,
                                             bool do_v, int32_t& cu, int32_t& cv) {
   int32_t* c = sim ? A.lower : A.upper;
   const int32_t d = sim ? 1 : -1;
+  do_u = do_u && (sim || ev.du <= kUpperMaxDegree);
+  do_v = do_v && (sim || ev.dv <= kUpperMaxDegree);
   cu = do_u ? atomicAdd(c + ev.u, d) : 0;
   cv = do_v ? atomicAdd(c + ev.v, d) : 0;
 }
 
 __device__ __forceinline__ void cores_roles(const EdgeArgs& A, const EdgeView& ev, bool sim, bool do_u,
                                             bool do_v, int32_t cu, int32_t cv) {
+  do_u = do_u && (sim || ev.du <= kUpperMaxDegree);
+  do_v = do_v && (sim || ev.dv <= kUpperMaxDegree);
   if (sim) {
     if (do_u && cu + 1 >= ev.mu) st_u8(A.role + ev.u, ROLE_CORE);
     if (do_v && cv + 1 >= ev.mu) st_u8(A.role + ev.v, ROLE_CORE);
@@ -544,10 +555,11 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ int64_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
   __shared__ int32_t s_n, s_min, s_chunk;
-  // cores pass: similar / dissimilar verdicts of this job's edges on the common
-  // larger side v, applied to v's bounds once per job (all of a job's edges
-  // would otherwise update the same two counters one by one)
-  __shared__ int32_t s_vsim, s_vdis;
+  // cores pass: similar verdicts of this job's edges on the common larger side
+  // v, added to v's lower bound once per job (all of a job's edges would
+  // otherwise update the same counter one by one); v's degree is above
+  // kUpperMaxDegree, so its upper bound is not kept
+  __shared__ int32_t s_vsim;
   const int tid = threadIdx.x;
   const int sub = tid & (kHubGroup - 1);  // lane within its group
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
@@ -558,7 +570,6 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
       s_job = (int64_t)atomicAdd(counter, 1ull);
       s_n = 0;
       s_vsim = 0;
-      s_vdis = 0;
     }
     __syncthreads();
     const int64_t job = s_job;
@@ -589,7 +600,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         n_eval += trivial ? 1 : 0;
       }
       if (MODE == MODE_CORES) {
-        int32_t cu[kHubPerThread], cv[kHubPerThread], vsim = 0, vdis = 0;
+        int32_t cu[kHubPerThread], cv[kHubPerThread], vsim = 0;
 #pragma unroll
         for (int i = 0; i < kHubPerThread; ++i)
           if (act[i]) cores_count(A, ev[i], sim[i], ev[i].open_u, false, cu[i], cv[i]);
@@ -598,13 +609,9 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           if (!act[i]) continue;
           A.state[J.begin + base + i * kHubBlock + tid] = sim[i] ? SIM_YES : SIM_NO;
           cores_roles(A, ev[i], sim[i], ev[i].open_u, false, cu[i], cv[i]);
-          if (ev[i].open_v) {
-            vsim += sim[i] ? 1 : 0;
-            vdis += sim[i] ? 0 : 1;
-          }
+          if (ev[i].open_v && sim[i]) ++vsim;
         }
         if (vsim) atomicAdd(&s_vsim, vsim);
-        if (vdis) atomicAdd(&s_vdis, vdis);
       } else {
 #pragma unroll
         for (int i = 0; i < kHubPerThread; ++i)
@@ -836,19 +843,18 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           cores_count(A, ev, sim, ev.open_u, false, cu, cv);
           A.state[e] = sim ? SIM_YES : SIM_NO;
           cores_roles(A, ev, sim, ev.open_u, false, cu, cv);
-          if (ev.open_v) atomicAdd(sim ? &s_vsim : &s_vdis, 1);
+          if (ev.open_v && sim) atomicAdd(&s_vsim, 1);
         } else {
           apply<MODE>(A, e, ev, MODE == MODE_COUNTS ? false : sim, cnt + 2);
         }
       }
       __syncthreads();
     }
-    if (MODE == MODE_CORES && tid == 0 && (s_vsim | s_vdis)) {
+    if (MODE == MODE_CORES && tid == 0 && s_vsim) {
       uint64_t gp, gq;
       int32_t vmu;
       graph_params(A, J.v, gp, gq, vmu);
-      if (s_vsim && atomicAdd(A.lower + J.v, s_vsim) + s_vsim >= vmu) st_u8(A.role + J.v, ROLE_CORE);
-      if (s_vdis && atomicSub(A.upper + J.v, s_vdis) - s_vdis < vmu) st_u8(A.role + J.v, ROLE_NONCORE);
+      if (atomicAdd(A.lower + J.v, s_vsim) + s_vsim >= vmu) st_u8(A.role + J.v, ROLE_CORE);
     }
     __syncthreads();  // every thread is done with this job's shared values
   }
