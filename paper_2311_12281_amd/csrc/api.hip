@@ -58,7 +58,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 
-constexpr int kCounters = 4;
+constexpr int kCounters = 5;  // job counters of the LDS-hash kernel per pass, then the number of cores
 
 }  // namespace
 
@@ -111,7 +111,8 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
     mark(SCAN_NUM_PHASES + 1 + k);
   }
   mark(2);
-  launch_finalize_roles(s, n, A.mu, g->d_lower, g->d_role, A.gid, A.gmu);
+  launch_finalize_roles(s, n, A.mu, g->d_lower, g->d_role, A.gid, A.gmu, g->d_counters + 4);
+  A.ncores = g->d_counters + 4;
   mark(3);
   launch_hook(s, m, g->d_edges, g->d_state, g->d_role, g->d_parent);
   mark(4);

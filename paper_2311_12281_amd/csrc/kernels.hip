@@ -355,6 +355,7 @@ __device__ __forceinline__ T shfl_t(T x, int src) {
 template <int MODE, int G, bool STAGE = false>
 __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
   static_assert(!STAGE || G == 64, "staging is per wave");
+  if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
   __shared__ int32_t stage[STAGE ? (kBlock / 64) * kHubMinDegree : 1];
   constexpr int kGroups = 64 / G;
   const int lane = threadIdx.x & 63;
@@ -565,6 +566,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
   const int4* T4 = reinterpret_cast<const int4*>(table);
   unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
+  if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
   while (true) {
     if (tid == 0) {
       s_job = (int64_t)atomicAdd(counter, 1ull);
@@ -899,13 +901,23 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 }
 
 __global__ void k_finalize(int32_t n, int32_t mu, const int32_t* gid, const int32_t* gmu, const int32_t* lower,
-                           uint8_t* role) {
+                           uint8_t* role, unsigned long long* ncores) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  if (gid) mu = gmu[gid[u]];
-  // A role still unknown here had every incident edge evaluated (an edge is
-  // only deferred when both roles are known), so lower is |N_eps[u]| exactly.
-  if (role[u] == ROLE_UNK) role[u] = lower[u] >= mu ? ROLE_CORE : ROLE_NONCORE;
+  bool core = false;
+  if (u < n) {
+    if (gid) mu = gmu[gid[u]];
+    // A role still unknown here had every incident edge evaluated (an edge is
+    // only deferred when both roles are known), so lower is |N_eps[u]| exactly.
+    uint8_t r = role[u];
+    if (r == ROLE_UNK) {
+      r = lower[u] >= mu ? ROLE_CORE : ROLE_NONCORE;
+      role[u] = r;
+    }
+    core = r == ROLE_CORE;
+  }
+  // cores counted so that the merge and attach passes can stop at once when there are none
+  const unsigned long long c = __popcll(__ballot(core));
+  if (ncores && (threadIdx.x & 63) == 0 && c) atomicAdd(ncores, c);
 }
 
 __global__ void k_hook(int64_t m, const int2* edges, const uint8_t* state, const uint8_t* role,
@@ -1126,8 +1138,8 @@ void launch_zero_u64(hipStream_t s, unsigned long long* p, int n) {
 }
 
 void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,
-                           const int32_t* gid, const int32_t* gmu) {
-  if (n > 0) k_finalize<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, gid, gmu, lower, role);
+                           const int32_t* gid, const int32_t* gmu, unsigned long long* ncores) {
+  if (n > 0) k_finalize<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, gid, gmu, lower, role, ncores);
 }
 
 void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,

@@ -104,6 +104,9 @@ struct EdgeArgs {
   const uint64_t* gp;
   const uint64_t* gq;
   const int32_t* gmu;
+  // Number of cores after the cores pass (null: unknown); the merge and attach
+  // kernels return at once when it is zero.
+  const unsigned long long* ncores;
 };
 
 // Launchers (kernels.hip)
@@ -123,8 +126,10 @@ int hub_grid_blocks();
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n);
 void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16);
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
+// ncores (optional): incremented by the number of cores after the pass.
 void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,
-                           const int32_t* gid = nullptr, const int32_t* gmu = nullptr);
+                           const int32_t* gid = nullptr, const int32_t* gmu = nullptr,
+                           unsigned long long* ncores = nullptr);
 void launch_hook(hipStream_t s, int64_t m, const int2* edges, const uint8_t* state,
                  const uint8_t* role, int32_t* parent);
 void launch_flatten(hipStream_t s, int32_t n, const uint8_t* role, int32_t* parent, int32_t* label);
