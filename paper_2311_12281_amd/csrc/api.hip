@@ -308,7 +308,7 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     return SCAN_OK;
   }
   CTRY(dalloc(&g->d_rp, (int64_t)n + 1), "hipMalloc row_ptr");
-  CTRY(dalloc(&g->d_ci, nnz), "hipMalloc col_idx");
+  CTRY(dalloc(&g->d_ci, nnz + kColPad), "hipMalloc col_idx");
   CTRY(hipMemcpyAsync(g->d_rp, row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, g->stream),
        "copy row_ptr");
   if (nnz > 0)

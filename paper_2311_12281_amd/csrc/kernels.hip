@@ -744,25 +744,26 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           // survivor's running totals itself, so no step needs a reduction
           // across the group.
           uint32_t my_hits = 0, my_seen = 0;
-          // elements of the next step are loaded while this one is probed
-          // (indices clamped into the chunk: every load is in bounds)
+          // elements of the next step are loaded while this one is probed;
+          // loads may run up to two steps past the chunk (col_idx is padded),
+          // values at or beyond ce are ignored
+          const int32_t* P = Arow + cs + sub;
           int32_t xn[kHubUnroll];
 #pragma unroll
-          for (int j = 0; j < kHubUnroll; ++j) {
-            const int32_t i = cs + j * kHubGroup + sub;
-            xn[j] = Arow[i < ce ? i : ce - 1];
-          }
+          for (int j = 0; j < kHubUnroll; ++j) xn[j] = P[j * kHubGroup];
           for (int32_t p = cs; p < ce; p += kStep) {
+            P += kStep;
+            const int32_t left = ce - p - sub;  // this lane's elements from here on
             int32_t x[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              x[j] = (p + j * kHubGroup + sub < ce) ? xn[j] : kHubNone;
-              const int32_t i = p + kStep + j * kHubGroup + sub;
-              xn[j] = Arow[i < ce ? i : ce - 1];
+              x[j] = (j * kHubGroup < left) ? xn[j] : kHubNone;
+              xn[j] = P[j * kHubGroup];
             }
             // first buckets of all elements, then second buckets, in the same registers
             int4 q[kHubUnroll];
-            uint32_t d[kHubUnroll], b2[kHubUnroll], full = 0;
+            uint32_t d[kHubUnroll], b2[kHubUnroll];
+            int32_t w1[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               uint32_t b1;
@@ -774,25 +775,27 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               const uint32_t xj = (uint32_t)x[j];
               d[j] = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
                          min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
-              full |= (uint32_t)(q[j].w != -1) << j;
+              w1[j] = q[j].w;
             }
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) q[j] = T4[b2[j]];
-            uint32_t step_hits = 0, step_seen = 0, tail = 0;
+            uint32_t step_hits = 0;
+            int32_t both_full = -1;  // >= 0 once some element had both buckets full
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               const uint32_t xj = (uint32_t)x[j];
               const uint32_t dj = min(d[j], min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
                                                 min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj)));
               step_hits += (dj == 0u);
-              step_seen += (x[j] != kHubNone);
-              // both buckets full and x in neither: it may sit further on
-              tail |= (uint32_t)((dj != 0u) & ((full >> j) & 1u) & (q[j].w != -1)) << j;
+              d[j] = dj;
+              // a bucket is full when its last slot holds an id (>= 0); empty slots hold -1
+              both_full = max(both_full, w1[j] | q[j].w);
             }
-            if (__ballot(tail != 0u)) {  // rare: both of an element's buckets full
+            const uint32_t step_seen = (uint32_t)min(max((left + kHubGroup - 1) / kHubGroup, 0), kHubUnroll);
+            if (__ballot(both_full >= 0)) {  // rare: both of some element's buckets full
 #pragma unroll
               for (int j = 0; j < kHubUnroll; ++j)
-                if ((tail >> j) & 1u) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
+                if (d[j] != 0u && (w1[j] | q[j].w) >= 0) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
             }
             if (exact) {
               my_hits += step_hits;

@@ -67,6 +67,10 @@ constexpr int kHubInsertBatch = 4; // table inserts per thread with their loads 
 constexpr int kHubGroup = 16;      // lanes streaming one survivor
 constexpr int kHubUnroll = 8;      // elements per lane per step
 constexpr int kHubChunk = 2048;    // elements of one survivor handed to a group at a time
+// col_idx is allocated with this many spare elements after its end, so that the
+// LDS-hash kernel's step loads (up to two steps past a chunk's end, values
+// beyond the end ignored) need no clamping
+constexpr int64_t kColPad = 2 * kHubGroup * kHubUnroll;
 constexpr int kHubLog2Slots = 15;  // LDS hash table: 32768 int32 slots = 128 KiB
 constexpr int kHubSlots = 1 << kHubLog2Slots;
 constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
