@@ -20,6 +20,7 @@ struct PartChunk {
   int32_t bi, bj;                          // block pair, bi <= bj
   int64_t begin, end;                      // range of the pinned edge array
   int64_t bucket_off[kNumBuckets + 1];     // bucket sub-ranges, clipped to [begin, end)
+  int64_t job_off = 0, job_cnt = 0;        // LDS-hash jobs of the last bucket (chunk-relative edges)
 };
 
 struct PartPlan {
@@ -33,10 +34,18 @@ struct PartPlan {
   int64_t row_cap = 0;            // ints of the device row buffer (two blocks)
   int64_t chunk_cap = 0;          // edges per chunk
   int32_t* d_rows = nullptr;
-  int2* d_edges = nullptr;
-  uint8_t* d_state = nullptr;
+  int2* d_edges = nullptr;        // two chunk buffers (edges, states): the next chunk is
+  uint8_t* d_state = nullptr;     // uploaded on the copy stream while kernels run on the other
+  int2* d_edges2 = nullptr;
+  uint8_t* d_state2 = nullptr;
   int32_t* d_ecount = nullptr;
+  HubJob* d_jobs = nullptr;       // every chunk's LDS-hash jobs (resident)
+  int32_t* d_worklist = nullptr;  // one slot per edge of a chunk
+  unsigned long long* d_jobctr = nullptr;
+  hipStream_t copy = nullptr;     // upload stream (default priority)
+  hipEvent_t up[2] = {}, done[2] = {};
   uint64_t h2d_bytes = 0;         // bytes sent to the device by the last call
+  int64_t chunks_streamed = 0;    // chunks sent by the last call (passes that skip chunks send fewer)
 };
 
 struct scan_graph {

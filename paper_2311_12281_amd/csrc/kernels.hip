@@ -627,8 +627,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
     }
     __syncthreads();
     const int32_t S = s_n;
-    const int64_t bv = A.rp[J.v];
-    const int64_t dv = A.rp[J.v + 1] - bv;
+    const int64_t bv = row_start(A, J.v);
+    const int64_t dv = A.rp[J.v + 1] - A.rp[J.v];
     // Phase B
     for (int32_t b0 = 0; b0 < S; b0 += kHubBatch) {
       const int32_t nbatch = (S - b0 < kHubBatch) ? S - b0 : kHubBatch;

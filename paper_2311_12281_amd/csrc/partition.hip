@@ -32,11 +32,15 @@ uint64_t inmemory_footprint(int32_t n, int64_t nnz) {
 
 namespace {
 
-constexpr uint64_t kEdgeBytes = 8 + 1 + 4;  // streamed per edge: endpoints, state, count
+// device bytes per chunk edge: two buffers of (endpoints, state), one count,
+// one worklist slot
+constexpr uint64_t kEdgeBytes = 2 * (8 + 1) + 4 + 4;
 
-int bucket_small(int64_t ds) {  // the group kernels' buckets (no LDS-hash bucket here)
+// the in-memory layout's buckets: by the smaller degree, and the LDS-hash
+// bucket for edges whose larger side has more than kHubMinDegree neighbours
+int part_bucket(int64_t ds, int64_t dl) {
   const int b = bucket_of(ds);
-  return b < 5 ? b : 5;
+  return (b == kNumBuckets - 2 && dl > kHubMinDegree) ? kNumBuckets - 1 : b;
 }
 
 }  // namespace
@@ -47,9 +51,15 @@ void part_release(scan_graph* g) {
   if (P.h_edges) (void)hipHostFree(P.h_edges);
   if (P.h_state) (void)hipHostFree(P.h_state);
   if (P.h_ecount) (void)hipHostFree(P.h_ecount);
-  void* d[] = {P.d_rows, P.d_edges, P.d_state, P.d_ecount};
+  void* d[] = {P.d_rows, P.d_edges, P.d_state, P.d_edges2, P.d_state2, P.d_ecount, P.d_jobs, P.d_worklist,
+               P.d_jobctr};
   for (void* p : d)
     if (p) (void)hipFree(p);
+  for (int b = 0; b < 2; ++b) {
+    if (P.up[b]) (void)hipEventDestroy(P.up[b]);
+    if (P.done[b]) (void)hipEventDestroy(P.done[b]);
+  }
+  if (P.copy) (void)hipStreamDestroy(P.copy);
   P = PartPlan();
 }
 
@@ -115,7 +125,7 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
   };
   auto pair_index = [&](int32_t i, int32_t j) { return (int64_t)i * K - (int64_t)i * (i - 1) / 2 + (j - i); };
   const int64_t npairs = (int64_t)K * (K + 1) / 2;
-  const int NB = kNumBuckets - 1 + 1;  // buckets 0..5
+  const int NB = kNumBuckets;
   std::vector<int64_t> cnt((size_t)(npairs * NB), 0);
   const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   // an edge {u, v} is listed from the row of its endpoint in the lower block
@@ -129,7 +139,7 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
         if (j < i || (j == i && v < u)) continue;
         const int64_t du = rp[u + 1] - rp[u], dv = rp[v + 1] - rp[v];
         const bool u_small = du < dv || (du == dv && u < v);
-        fn(j, u_small ? u : v, u_small ? v : u, bucket_small(u_small ? du : dv));
+        fn(j, u_small ? u : v, u_small ? v : u, u_small ? part_bucket(du, dv) : part_bucket(dv, du));
       }
     }
   };
@@ -169,6 +179,19 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
     for (auto& x : th) x.join();
   }
   if (nnz > 0) memcpy(P.h_ci, ci, sizeof(int32_t) * (size_t)nnz);
+  {
+    // the last bucket of every pair grouped by the larger side, as the LDS-hash jobs need
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        for (int64_t pi = t; pi < npairs; pi += nth) {
+          int2* b = P.h_edges + off[(size_t)(pi * NB + NB - 1)];
+          int2* e = P.h_edges + off[(size_t)(pi * NB + NB)];
+          std::sort(b, e, [](const int2& x, const int2& y) { return x.y != y.y ? x.y < y.y : x.x < y.x; });
+        }
+      });
+    for (auto& x : th) x.join();
+  }
   // chunks: runs of one pair of at most chunk_cap edges
   for (int32_t i = 0; i < K; ++i)
     for (int32_t j = i; j < K; ++j) {
@@ -187,13 +210,59 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
         P.chunks.push_back(C);
       }
     }
+  // LDS-hash jobs of each chunk's last bucket: runs of one larger side, cut like
+  // the in-memory job table, heaviest larger side first; edges chunk-relative
+  std::vector<HubJob> jobs;
+  for (PartChunk& C : P.chunks) {
+    C.job_off = (int64_t)jobs.size();
+    const int64_t b6 = C.bucket_off[kNumBuckets - 1], e6 = C.bucket_off[kNumBuckets];
+    for (int64_t k = b6; k < e6;) {
+      const int32_t v = P.h_edges[k].y;
+      HubJob J;
+      J.v = v;
+      J.begin = k - C.begin;
+      J.count = 0;
+      int64_t work = 0;
+      while (k < e6 && P.h_edges[k].y == v) {
+        const int64_t du = rp[P.h_edges[k].x + 1] - rp[P.h_edges[k].x];
+        if (J.count > 0 && (J.count == kHubJobEdges || work + du > kHubJobWork)) {
+          jobs.push_back(J);
+          J.begin = k - C.begin;
+          J.count = 0;
+          work = 0;
+        }
+        ++J.count;
+        work += du;
+        ++k;
+      }
+      jobs.push_back(J);
+    }
+    C.job_cnt = (int64_t)jobs.size() - C.job_off;
+    std::stable_sort(jobs.begin() + C.job_off, jobs.end(), [&](const HubJob& a, const HubJob& b) {
+      return rp[a.v + 1] - rp[a.v] > rp[b.v + 1] - rp[b.v];
+    });
+  }
   P.row_cap = row_cap;
   P.chunk_cap = chunk_cap;
-  if ((e = hipMalloc((void**)&P.d_rows, sizeof(int32_t) * (size_t)std::max<int64_t>(row_cap, 1))) != hipSuccess ||
+  // rows are read up to kColPad elements past their end by the LDS-hash kernel
+  if ((e = hipMalloc((void**)&P.d_rows, sizeof(int32_t) * (size_t)(std::max<int64_t>(row_cap, 1) + kColPad))) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_jobs, sizeof(HubJob) * std::max<size_t>(jobs.size(), 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_worklist, sizeof(int32_t) * (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_jobctr, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_edges, sizeof(int2) * (size_t)chunk_cap)) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_state, (size_t)chunk_cap)) != hipSuccess ||
-      (e = hipMalloc((void**)&P.d_ecount, sizeof(int32_t) * (size_t)chunk_cap)) != hipSuccess)
+      (e = hipMalloc((void**)&P.d_edges2, sizeof(int2) * (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_state2, (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_ecount, sizeof(int32_t) * (size_t)chunk_cap)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&P.copy, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.up[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.up[1], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.done[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.done[1], hipEventDisableTiming)) != hipSuccess)
     return fail_hip(e, "device buffers");
+  if (!jobs.empty() &&
+      (e = hipMemcpy(P.d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail_hip(e, "job table");
   g->partitioned = true;
   g->m = m;
   return SCAN_OK;
@@ -241,6 +310,59 @@ struct Streamer {
 
 }  // namespace
 
+namespace {
+
+// The kernels of one resident chunk: group kernels for buckets 0-5, the
+// LDS-hash kernel with the chunk's own jobs for the last bucket.
+void launch_chunk(hipStream_t s, int mode, const PartChunk& C, EdgeArgs& A, PartPlan& P) {
+  for (int k = 0; k < kNumBuckets; ++k) {
+    A.e_begin = C.bucket_off[k] - C.begin;
+    A.e_end = C.bucket_off[k + 1] - C.begin;
+    A.bucket = k;
+    if (k < kNumBuckets - 1) {
+      launch_edges(s, mode, k, A);
+    } else if (C.job_cnt > 0) {
+      launch_zero_u64(s, P.d_jobctr, 1);
+      launch_hub(s, mode, A, P.d_jobs + C.job_off, C.job_cnt, P.d_jobctr, P.d_worklist);
+    }
+  }
+}
+
+// Chunks the merge pass (some edge with two core endpoints) and the attach pass
+// (some edge with exactly one core endpoint whose state is not dissimilar) must
+// stream; host threads over the chunks.
+void select_chunks(const PartPlan& P, const uint8_t* role, std::vector<int32_t>& merge_list,
+                   std::vector<int32_t>& attach_list) {
+  const size_t nc = P.chunks.size();
+  std::vector<uint8_t> need_m(nc, 0), need_a(nc, 0);
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      for (size_t c = t; c < nc; c += nth) {
+        const PartChunk& C = P.chunks[c];
+        bool m = false, a = false;
+        for (int64_t e = C.begin; e < C.end && !(m && a); ++e) {
+          const int2 uv = P.h_edges[e];
+          const bool cu = role[uv.x] == ROLE_CORE, cv = role[uv.y] == ROLE_CORE;
+          m = m || (cu && cv);
+          a = a || (cu != cv && P.h_state[e] != SIM_NO);
+        }
+        need_m[c] = m;
+        need_a[c] = a;
+      }
+    });
+  for (auto& x : th) x.join();
+  merge_list.clear();
+  attach_list.clear();
+  for (size_t c = 0; c < nc; ++c) {
+    if (need_m[c]) merge_list.push_back((int32_t)c);
+    if (need_a[c]) attach_list.push_back((int32_t)c);
+  }
+}
+
+}  // namespace
+
 int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_labels, uint8_t* d_roles,
              hipStream_t s) {
   PartPlan& P = g->part;
@@ -269,6 +391,13 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
   launch_init(s, n, g->d_rp, mu, g->d_lower, g->d_upper, g->d_role, g->d_parent);
   if (g->m > 0) memset(P.h_state, SIM_UNK, (size_t)g->m);
   mark(1);
+  // Chunks each pass streams: all of them for the cores pass; after it, only
+  // those holding an edge the pass can act on (merge: both endpoints cores;
+  // attach: one core, one non-core, not known dissimilar), found on the host
+  // from the final roles and the edge states.
+  std::vector<int32_t> all((size_t)P.chunks.size()), merge_list, attach_list;
+  for (size_t c = 0; c < all.size(); ++c) all[c] = (int32_t)c;
+  P.chunks_streamed = 0;
   const int modes[3] = {MODE_CORES, MODE_MERGE, MODE_ATTACH};
   for (int mi = 0; mi < 3; ++mi) {
     const int mode = modes[mi];
@@ -276,34 +405,48 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
       mark(2);
       launch_finalize_roles(s, n, mu, g->d_lower, g->d_role);
       mark(3);
+      std::vector<uint8_t> role((size_t)n);
+      if (n > 0) HIP_TRY(hipMemcpyAsync(role.data(), g->d_role, (size_t)n, hipMemcpyDeviceToHost, s), "roles D2H");
+      HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+      select_chunks(P, role.data(), merge_list, attach_list);
       mark(4);
     } else if (mode == MODE_ATTACH) {
       mark(5);
       launch_flatten(s, n, g->d_role, g->d_parent, g->d_label);
       mark(6);
     }
+    const std::vector<int32_t>& list = mode == MODE_CORES ? all : mode == MODE_MERGE ? merge_list : attach_list;
     Streamer st{g, s};
-    for (const PartChunk& C : P.chunks) {
+    int idx = 0;
+    for (const int32_t ci : list) {
+      const PartChunk& C = P.chunks[(size_t)ci];
       const int64_t ne = C.end - C.begin;
-      HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
-      HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
+      const int b = idx & 1;
+      int2* de = b ? P.d_edges2 : P.d_edges;
+      uint8_t* ds = b ? P.d_state2 : P.d_state;
+      // upload on the copy stream once the chunk that last used this buffer is done
+      if (idx >= 2) HIP_TRY(hipStreamWaitEvent(P.copy, P.done[b], 0), "hipStreamWaitEvent");
+      HIP_TRY(hipMemcpyAsync(de, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, P.copy),
               "edges H2D");
-      HIP_TRY(hipMemcpyAsync(P.d_state, P.h_state + C.begin, (size_t)ne, hipMemcpyHostToDevice, s), "state H2D");
+      HIP_TRY(hipMemcpyAsync(ds, P.h_state + C.begin, (size_t)ne, hipMemcpyHostToDevice, P.copy), "state H2D");
+      HIP_TRY(hipEventRecord(P.up[b], P.copy), "hipEventRecord");
       P.h2d_bytes += 9ull * (uint64_t)ne;
-      if (mode == MODE_MERGE) launch_hook(s, ne, P.d_edges, P.d_state, g->d_role, g->d_parent);
-      for (int b = 0; b < kNumBuckets - 1; ++b) {
-        A.e_begin = C.bucket_off[b] - C.begin;
-        A.e_end = C.bucket_off[b + 1] - C.begin;
-        A.bucket = b;
-        launch_edges(s, mode, b, A);
-      }
+      ++P.chunks_streamed;
+      // block rows go on the compute stream: the previous chunk's kernels read the old ones
+      HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
+      HIP_TRY(hipStreamWaitEvent(s, P.up[b], 0), "hipStreamWaitEvent");
+      A.edges = de;
+      A.state = ds;
+      if (mode == MODE_MERGE) launch_hook(s, ne, de, ds, g->d_role, g->d_parent);
+      launch_chunk(s, mode, C, A, P);
       if (mode != MODE_ATTACH)
-        HIP_TRY(hipMemcpyAsync(P.h_state + C.begin, P.d_state, (size_t)ne, hipMemcpyDeviceToHost, s), "state D2H");
-      // The next chunk overwrites the device buffers and the host reuses them
-      // only through stream order; the state copy back must land before the
-      // next pass reads P.h_state, which the synchronisation below ensures.
+        HIP_TRY(hipMemcpyAsync(P.h_state + C.begin, ds, (size_t)ne, hipMemcpyDeviceToHost, s), "state D2H");
+      HIP_TRY(hipEventRecord(P.done[b], s), "hipEventRecord");
+      ++idx;
     }
+    // the states copied back are read by the next pass's uploads and chunk selection
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(P.copy), "hipStreamSynchronize");
   }
   mark(7);
   const int32_t split = g->opts.hub_outlier ? 1 : 0;
@@ -368,12 +511,7 @@ int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
     HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
     HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
             "edges H2D");
-    for (int b = 0; b < kNumBuckets - 1; ++b) {
-      A.e_begin = C.bucket_off[b] - C.begin;
-      A.e_end = C.bucket_off[b + 1] - C.begin;
-      A.bucket = b;
-      launch_edges(s, MODE_COUNTS, b, A);
-    }
+    launch_chunk(s, MODE_COUNTS, C, A, P);
     HIP_TRY(hipMemcpyAsync(P.h_ecount + C.begin, P.d_ecount, sizeof(int32_t) * (size_t)ne, hipMemcpyDeviceToHost, s),
             "counts D2H");
   }
