@@ -442,16 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 //   Phase A: every thread classifies in-edges; those needing an intersection
 //            are appended to the job's slice of the worklist.
 //   Phase B: the survivors are processed kHubBatch at a time.  For each batch
-//            the block fills an LDS hash table with nbr(v) (multiplicative
-//            hash, linear probing, at most half full) and every wave streams
-//            the smaller lists nbr(u_i) of its survivors through it, 64 probes
-//            per step, counting hits with a ballot.  Rows longer than the
-//            table are taken in windows of kHubWindow consecutive elements of
-//            nbr(v); a window holds the values below the first element of the
-//            next one, and each survivor keeps its read position and next
-//            element in LDS, so nbr(u_i) is read once in total and windows
-//            below every survivor's next element are not built at all.  A
-//            survivor stops as soon as its verdict is certain.
+//            the block loads nbr(v) into LDS, window by window, and groups of
+//            kHubGroup lanes stream the smaller lists nbr(u_i) of the
+//            survivors through it.  A window is a run of consecutive elements
+//            of nbr(v) and stands for the ids from its first element up to
+//            the first element of the next window, so each survivor keeps its
+//            read position and next element in LDS, nbr(u_i) is read once in
+//            total, and windows below every survivor's next element are not
+//            built at all.  Where kHubBitmapBits ids from the window's first
+//            element on hold at least kHubBitmapMin elements of nbr(v), the
+//            window is all of them, kept as a bitmap (a probe is one bit
+//            test); otherwise it is the next kHubWindow elements, kept as a
+//            hash set.  A survivor stops as soon as its verdict is certain.
 // LDS hash set: kHubSlots int32 slots viewed as buckets of 4 (one 16-byte
 // LDS load each).  Two-choice placement: every element has two buckets, both
 // derived from one multiplicative hash, and goes to the emptier one; only when
@@ -536,12 +538,43 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* wsum
   return off + incl - x;
 }
 
+template <bool B>
+struct KindTag {
+  static constexpr bool value = B;
+};
+
+// First index in (lo, hi) whose value is at least T in the ascending array
+// row, or hi if there is none; row[lo] < T.  The whole block searches
+// together, one load per thread per round, each round narrowing the range
+// kHubBlock-fold.  Every thread must call it with the same arguments.
+__device__ __forceinline__ int64_t block_find(const int32_t* row, int64_t lo, int64_t hi, int64_t T,
+                                              int32_t* s_first) {
+  while (hi - lo > 1) {
+    const int64_t stride = (hi - lo - 1 + kHubBlock - 1) / kHubBlock;
+    if (threadIdx.x == 0) *s_first = kHubBlock;
+    __syncthreads();
+    const int64_t p = lo + (int64_t)(threadIdx.x + 1) * stride;
+    if (p < hi && (int64_t)row[p] >= T) atomicMin(s_first, (int32_t)threadIdx.x);
+    __syncthreads();
+    const int32_t t = *s_first;
+    __syncthreads();  // s_first is reset at the top of the next round
+    if (t < kHubBlock) {
+      hi = lo + (int64_t)(t + 1) * stride;
+      lo = lo + (int64_t)t * stride;
+    } else {
+      lo = lo + ((hi - 1 - lo) / stride) * stride;  // the last probe below hi
+    }
+  }
+  return hi;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs,
                                                    unsigned long long* counter, int32_t* wl) {
   constexpr int kGroups = kHubBlock / kHubGroup;
   constexpr int kStep = kHubGroup * kHubUnroll;  // elements per group step
-  __shared__ __align__(16) int32_t table[kHubSlots];
+  // hash set, or bitmap plus one zero word that out-of-range probes read
+  __shared__ __align__(16) int32_t table[kHubSlots + 4];
   __shared__ int64_t q_bu[kHubBatch];
   __shared__ unsigned long long q_acc[kHubBatch];  // (consumed in this window) << 32 | hits
   __shared__ int32_t q_du[kHubBatch];
@@ -555,7 +588,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
   __shared__ uint8_t q_st[kHubBatch];     // 0 skipped, 1 active, 2 similar, 3 dissimilar
   __shared__ int64_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
-  __shared__ int32_t s_n, s_min, s_chunk;
+  __shared__ int32_t s_n, s_min, s_chunk, s_first;
   // cores pass: similar verdicts of this job's edges on the common larger side
   // v, added to v's lower bound once per job (all of a job's edges would
   // otherwise update the same counter one by one); v's degree is above
@@ -645,8 +678,20 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         q_next[tid] = (keep && ev.du > 0) ? A.ci[ev.bu] : INT_MAX;
         q_st[tid] = keep ? 1 : 0;
       }
-      for (int64_t w0 = 0; w0 < dv; w0 += kHubWindow) {
-        const int64_t w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+      for (int64_t w0 = 0, w1 = 0; w0 < dv; w0 = w1) {
+        // This window is a bitmap of the ids L .. L + kHubBitmapBits - 1 if
+        // that range holds at least kHubBitmapMin elements of nbr(v) from w0
+        // on, else a hash set of the next kHubWindow elements.
+        const int32_t L = A.ci[bv + w0];
+        bool bitmap = false;
+        w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+        if (dv - w0 >= kHubBitmapMin) {
+          const int64_t wb = block_find(A.ci + bv, w0, dv, (int64_t)L + kHubBitmapBits, &s_first);
+          if (wb - w0 >= kHubBitmapMin) {
+            bitmap = true;
+            w1 = wb;
+          }
+        }
         const int32_t hi = (w1 < dv) ? A.ci[bv + w1] : INT_MAX;
         if (tid == 0) {
           s_min = INT_MAX;
@@ -659,7 +704,11 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         __syncthreads();           // s_min is reset at the top of the next window
         if (mn == INT_MAX) break;  // every survivor decided or fully read
         if (mn >= hi) continue;    // no survivor has an element in this window
-        for (int k = tid; k < kHubSlots; k += kHubBlock) table[k] = -1;
+        if (bitmap) {
+          for (int k = tid; k < kHubSlots + 4; k += kHubBlock) table[k] = 0;
+        } else {
+          for (int k = tid; k < kHubSlots; k += kHubBlock) table[k] = -1;
+        }
         // This window's part of every active survivor, cut into chunks of
         // kHubChunk.  Chunks are handed out first-chunk-of-every-survivor
         // first, then the remaining chunks survivor by survivor, so that most
@@ -708,8 +757,15 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             y[i] = (k < w1) ? A.ci[bv + k] : kHubNone;
           }
 #pragma unroll
-          for (int i = 0; i < kHubInsertBatch; ++i)
-            if (y[i] != kHubNone) hub_insert(table, y[i]);
+          for (int i = 0; i < kHubInsertBatch; ++i) {
+            if (y[i] == kHubNone) continue;
+            if (bitmap) {
+              const uint32_t off = (uint32_t)y[i] - (uint32_t)L;
+              atomicOr(reinterpret_cast<uint32_t*>(table) + (off >> 5), 1u << (off & 31));
+            } else {
+              hub_insert(table, y[i]);
+            }
+          }
         }
         __syncthreads();
         // Groups of kHubGroup lanes take chunks until none are left.  The loop
@@ -718,6 +774,9 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         // a branch on the lane index would let the compiler run the group's
         // lanes around the loop separately, and the shuffles need the whole
         // group together.
+        // the chunk loop, compiled once per kind of window
+        auto chunk_loop = [&](auto kind) {
+        constexpr bool kBitmap = decltype(kind)::value;
         while (true) {
           // every lane adds 1, so a group's lanes receive 16 consecutive
           // values starting at a multiple of kHubGroup: value / kHubGroup is
@@ -760,6 +819,18 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               x[j] = (j * kHubGroup < left) ? xn[j] : kHubNone;
               xn[j] = P[j * kHubGroup];
             }
+            uint32_t step_hits = 0;
+            const uint32_t step_seen = (uint32_t)min(max((left + kHubGroup - 1) / kHubGroup, 0), kHubUnroll);
+            if constexpr (kBitmap) {
+              // ids outside L .. L + kHubBitmapBits - 1 (kHubNone included)
+              // read the zero word just past the bitmap
+              const uint32_t* bm = reinterpret_cast<const uint32_t*>(table);
+#pragma unroll
+              for (int j = 0; j < kHubUnroll; ++j) {
+                const uint32_t off = min((uint32_t)x[j] - (uint32_t)L, (uint32_t)kHubBitmapBits);
+                step_hits += (bm[off >> 5] >> (off & 31)) & 1u;
+              }
+            } else {
             // first buckets of all elements, then second buckets, in the same registers
             int4 q[kHubUnroll];
             uint32_t d[kHubUnroll], b2[kHubUnroll];
@@ -779,7 +850,6 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             }
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) q[j] = T4[b2[j]];
-            uint32_t step_hits = 0;
             int32_t both_full = -1;  // >= 0 once some element had both buckets full
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
@@ -791,11 +861,11 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
               // a bucket is full when its last slot holds an id (>= 0); empty slots hold -1
               both_full = max(both_full, w1[j] | q[j].w);
             }
-            const uint32_t step_seen = (uint32_t)min(max((left + kHubGroup - 1) / kHubGroup, 0), kHubUnroll);
             if (__ballot(both_full >= 0)) {  // rare: both of some element's buckets full
 #pragma unroll
               for (int j = 0; j < kHubUnroll; ++j)
                 if (d[j] != 0u && (w1[j] | q[j].w) >= 0) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
+            }
             }
             if (exact) {
               my_hits += step_hits;
@@ -819,6 +889,9 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           }
           if (exact) atomicAdd(&q_acc[k], ((unsigned long long)my_seen << 32) | my_hits);
         }
+        };
+        if (bitmap) chunk_loop(KindTag<true>{});
+        else chunk_loop(KindTag<false>{});
         __syncthreads();
         if (tid < nbatch && q_st[tid] != 0 && q_next[tid] < hi) {
           // window finished for this survivor (or it was decided on the way)

@@ -74,6 +74,11 @@ constexpr int64_t kColPad = 2 * kHubGroup * kHubUnroll;
 constexpr int kHubLog2Slots = 15;  // LDS hash table: 32768 int32 slots = 128 KiB
 constexpr int kHubSlots = 1 << kHubLog2Slots;
 constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
+// The same LDS array read as a bitmap covers kHubBitmapBits consecutive ids;
+// a window of nbr(v) is taken as a bitmap when that many ids from its first
+// element on hold at least kHubBitmapMin elements of nbr(v).
+constexpr int kHubBitmapBits = kHubSlots * 32;
+constexpr int kHubBitmapMin = 4096;
 struct HubJob {
   int64_t begin;  // first edge of the job
   int32_t v;      // common larger side

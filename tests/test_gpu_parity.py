@@ -292,8 +292,43 @@ def test_full_survivor_batch():
     check_graph(g, [((1, 5), 3)], "full-survivor-batch-exhaustive", counts=False, pruning=False)
 
 
+def spread_hub_graph(seed=11, heavy=400):
+    """Vertex 0 has a neighbourhood whose ids are dense in some ranges and
+    sparse in others, so the LDS-hash kernel takes it as a bitmap window
+    (ids 1 .. 9000 and 2^20, the last bit of that window's id range), two
+    hash windows (33000 ids spread over 2^24 ids from 2^21 on, about 2000 per
+    2^20 ids) and a bitmap window again (the last spread ids with 6000
+    consecutive ids just after them).  Heavy neighbours of vertex 0 get
+    100 .. 300 more neighbours inside its neighbourhood and 0 .. 200 private
+    leaves, so their edges to the hub have a smaller side of degree > 64,
+    span every window and range from similar to dissimilar."""
+    rng = np.random.default_rng(seed)
+    spread = 2 ** 21 + rng.choice(2 ** 24, size=33000, replace=False)
+    dense = 2 ** 21 + 2 ** 24 + 1000 + np.arange(6000)
+    hub_nbrs = np.unique(np.concatenate([np.arange(1, 9001), [2 ** 20, 2 ** 20 + 1], spread, dense]))
+    leaf = int(dense[-1]) + 1
+    edges = [(0, int(w)) for w in hub_nbrs]
+    for u in rng.choice(hub_nbrs, size=heavy, replace=False):
+        n_in, n_out = int(rng.integers(100, 301)), int(rng.integers(0, 201))
+        for w in rng.choice(hub_nbrs, size=n_in, replace=False):
+            if int(w) != int(u):
+                edges.append((int(u), int(w)))
+        for _ in range(n_out):
+            edges.append((int(u), leaf))
+            leaf += 1
+    return gg.from_edges(leaf, edges)
+
+
+def test_bitmap_and_hash_windows():
+    """The hub's row is taken as bitmap, hash, hash and bitmap windows."""
+    g = spread_hub_graph()
+    check_graph(g, [((1, 12), 2), ((1, 16), 3), ((1, 25), 5), ((1, 40), 2)], "spread-hub")
+    check_graph(g, [((1, 16), 3)], "spread-hub-exhaustive", counts=False, pruning=False)
+
+
 @pytest.mark.parametrize("name,gen", [
     ("rmat16", lambda: gg.rmat(16, 16, seed=2)),
+    ("spread-hub", spread_hub_graph),
     ("windowed-hub", windowed_hub_graph),
     ("planted-A", lambda: gg.planted(10000, 50, 0.15, 0.0005, 1)),
 ])
