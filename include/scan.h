@@ -74,6 +74,13 @@ typedef struct scan_opts {
   int32_t hub_outlier;          /* 1: report SCAN_HUB / SCAN_OUTLIER instead of
                                    SCAN_UNCLASSIFIED (one more pass over the edges,
                                    Def 2.7 and Alg. 4); 0 (default): three roles */
+  int32_t hub_ranked;           /* 1 (default): on the in-memory path, for graphs of more
+                                   than 2^20 vertices, the edges whose smaller side has
+                                   degree > 64 intersect a copy of the rows in which every
+                                   vertex is renamed to its rank by increasing degree
+                                   (4 more device bytes per arc, built on the host when the
+                                   graph is created); 0: the rows as given.  Results are
+                                   identical either way. */
   void* hip_stream;             /* hipStream_t to run on; NULL = a library-owned stream */
 } scan_opts;
 

@@ -54,6 +54,7 @@ class scan_opts(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("strategy", ctypes.c_int32),
         ("hub_outlier", ctypes.c_int32),
+        ("hub_ranked", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
     ]
 
@@ -170,10 +171,12 @@ def scan_opts_default() -> scan_opts:
 
 
 def make_opts(budget: int = 0, validate: bool = True, pruning: bool = True, timing: bool = False,
-              strategy: int = 0, hub_outlier: bool = False, stream: int | None = None) -> scan_opts:
+              strategy: int = 0, hub_outlier: bool = False, hub_ranked: bool = True,
+              stream: int | None = None) -> scan_opts:
     o = scan_opts_default()
     o.strategy = int(strategy)
     o.hub_outlier = int(bool(hub_outlier))
+    o.hub_ranked = int(bool(hub_ranked))
     o.device_budget_bytes = int(budget)
     o.validate = int(bool(validate))
     o.pruning = int(bool(pruning))

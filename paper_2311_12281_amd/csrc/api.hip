@@ -43,7 +43,7 @@ namespace {
 
 void release(scan_graph* g) {
   part_release(g);
-  void* ptrs[] = {g->d_rp, g->d_ci, g->d_edges, g->d_jobs, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_jobs, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -88,6 +88,7 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   };
   A.rp = g->d_rp;
   A.ci = g->d_ci;
+  A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
   A.state = g->d_state;
   A.lower = g->d_lower;
@@ -204,6 +205,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   EdgeArgs A{};
   A.rp = g->d_rp;
   A.ci = g->d_ci;
+  A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
   A.counts = d_counts_arc;
   A.edge_counts = d_counts_edge;
@@ -240,6 +242,7 @@ void scan_opts_default(scan_opts* o) {
   memset(o, 0, sizeof(*o));
   o->validate = 1;
   o->pruning = 1;
+  o->hub_ranked = 1;
 }
 
 const char* scan_last_error(void) { return g_error.c_str(); }
@@ -285,7 +288,7 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     CTRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
     g->own_stream = true;
   }
-  if (g->opts.device_budget_bytes && inmemory_footprint(n, nnz) > g->opts.device_budget_bytes) {
+  if (g->opts.device_budget_bytes && inmemory_footprint(n, nnz, g->opts.hub_ranked != 0) > g->opts.device_budget_bytes) {
     // Partition-based path: the CSR stays in pinned host memory.
     rc = part_validate(n, nnz, row_ptr, col_idx, g->opts.validate != 0);
     if (rc != SCAN_OK) goto error;
@@ -323,6 +326,10 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
   }
   g->max_degree = lay.max_degree;
   g->hub_jobs = lay.hub_jobs;
+  if (g->opts.hub_ranked && n > kHubBitmapBits && lay.hub_jobs > 0) {
+    CTRY(dalloc(&g->d_hci, nnz + kColPad), "hipMalloc ranked rows");
+    CTRY(build_ranked_rows(g->stream, n, nnz, row_ptr, col_idx, g->d_hci), "ranked rows");
+  }
   for (int k = 0; k <= kNumBuckets; ++k) g->bucket_off[k] = lay.bucket_off[k];
   g->m = lay.bucket_off[kNumBuckets];
   if (g->opts.validate && g->m * 2 != nnz) {

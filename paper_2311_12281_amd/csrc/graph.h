@@ -62,6 +62,7 @@ struct scan_graph {
   // graph (read-only after create)
   int64_t* d_rp = nullptr;
   int32_t* d_ci = nullptr;
+  int32_t* d_hci = nullptr;  // rows renamed by degree rank (LDS-hash kernel), or null
   int2* d_edges = nullptr;
   HubJob* d_jobs = nullptr;
   int64_t hub_jobs = 0;
@@ -110,7 +111,7 @@ int fail_hip(hipError_t e, const char* what);
 int run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hipStream_t s);
 
 // Partitioned path (partition.hip).  device bytes the in-memory layout needs:
-uint64_t inmemory_footprint(int32_t n, int64_t nnz);
+uint64_t inmemory_footprint(int32_t n, int64_t nnz, bool ranked);
 // Plans blocks and chunks for `budget` device bytes, copies the CSR to pinned
 // memory and allocates the resident state and streaming buffers.
 int part_validate(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, bool full);

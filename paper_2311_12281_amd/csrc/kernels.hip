@@ -453,7 +453,11 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 //            element on hold at least kHubBitmapMin elements of nbr(v), the
 //            window is all of them, kept as a bitmap (a probe is one bit
 //            test); otherwise it is the next kHubWindow elements, kept as a
-//            hash set.  A survivor stops as soon as its verdict is certain.
+//            hash set, cut short where the longest suffix of nbr(v) that one
+//            bitmap covers begins.  A survivor stops as soon as its verdict
+//            is certain.  The rows may be given with vertices renamed by
+//            degree rank (A.hci), which packs most of a long row into the
+//            last bitmap window.
 // LDS hash set: kHubSlots int32 slots viewed as buckets of 4 (one 16-byte
 // LDS load each).  Two-choice placement: every element has two buckets, both
 // derived from one multiplicative hash, and goes to the emptier one; only when
@@ -662,6 +666,15 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
     const int32_t S = s_n;
     const int64_t bv = row_start(A, J.v);
     const int64_t dv = A.rp[J.v + 1] - A.rp[J.v];
+    // Start of the longest suffix of nbr(v) that one bitmap covers; when it
+    // holds at least kHubBitmapMin elements, hash windows stop at it, so that
+    // the suffix becomes a single bitmap window.
+    int64_t wsuf = dv;
+    if (S > 0 && dv >= kHubBitmapMin) {
+      const int64_t T = (int64_t)A.hci[bv + dv - 1] - kHubBitmapBits + 1;
+      const int64_t ws = ((int64_t)A.hci[bv] >= T) ? 0 : block_find(A.hci + bv, 0, dv, T, &s_first);
+      if (dv - ws >= kHubBitmapMin) wsuf = ws;
+    }
     // Phase B
     for (int32_t b0 = 0; b0 < S; b0 += kHubBatch) {
       const int32_t nbatch = (S - b0 < kHubBatch) ? S - b0 : kHubBatch;
@@ -675,24 +688,26 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         q_need[tid] = ev.need - 2;
         q_cnt[tid] = 0;
         q_pos[tid] = 0;
-        q_next[tid] = (keep && ev.du > 0) ? A.ci[ev.bu] : INT_MAX;
+        q_next[tid] = (keep && ev.du > 0) ? A.hci[ev.bu] : INT_MAX;
         q_st[tid] = keep ? 1 : 0;
       }
       for (int64_t w0 = 0, w1 = 0; w0 < dv; w0 = w1) {
         // This window is a bitmap of the ids L .. L + kHubBitmapBits - 1 if
         // that range holds at least kHubBitmapMin elements of nbr(v) from w0
-        // on, else a hash set of the next kHubWindow elements.
-        const int32_t L = A.ci[bv + w0];
+        // on, else a hash set of the next kHubWindow elements (at most up to
+        // the bitmap suffix).
+        const int32_t L = A.hci[bv + w0];
         bool bitmap = false;
         w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+        if (w0 < wsuf && w1 > wsuf) w1 = wsuf;
         if (dv - w0 >= kHubBitmapMin) {
-          const int64_t wb = block_find(A.ci + bv, w0, dv, (int64_t)L + kHubBitmapBits, &s_first);
+          const int64_t wb = block_find(A.hci + bv, w0, dv, (int64_t)L + kHubBitmapBits, &s_first);
           if (wb - w0 >= kHubBitmapMin) {
             bitmap = true;
             w1 = wb;
           }
         }
-        const int32_t hi = (w1 < dv) ? A.ci[bv + w1] : INT_MAX;
+        const int32_t hi = (w1 < dv) ? A.hci[bv + w1] : INT_MAX;
         if (tid == 0) {
           s_min = INT_MAX;
           s_chunk = 0;
@@ -719,7 +734,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         if (tid < nbatch) {
           q_acc[tid] = 0;
           if (q_st[tid] == 1 && q_next[tid] < hi) {
-            const int32_t* Arow = A.ci + q_bu[tid];
+            const int32_t* Arow = A.hci + q_bu[tid];
             int32_t lo = q_pos[tid], hi2 = q_du[tid];
             if (hi != INT_MAX) {
               while (lo < hi2) {
@@ -754,7 +769,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
 #pragma unroll
           for (int i = 0; i < kHubInsertBatch; ++i) {
             const int64_t k = k0 + (int64_t)i * kHubBlock;
-            y[i] = (k < w1) ? A.ci[bv + k] : kHubNone;
+            y[i] = (k < w1) ? A.hci[bv + k] : kHubNone;
           }
 #pragma unroll
           for (int i = 0; i < kHubInsertBatch; ++i) {
@@ -795,7 +810,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           }
           const int k = lo;
           if (q_st[k] != 1) continue;  // already decided
-          const int32_t* Arow = A.ci + q_bu[k];
+          const int32_t* Arow = A.hci + q_bu[k];
           const int32_t base = q_pos[k], du = q_du[k], need = q_need[k], cnt0 = q_cnt[k];
           const int32_t cs = first ? base : base + (1 + cc - pre[k]) * kHubChunk;
           const int32_t ce = (q_end[k] - cs < kHubChunk) ? q_end[k] : cs + kHubChunk;
@@ -901,7 +916,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           q_cnt[tid] = cnt;
           q_pos[tid] = pos;
           if (q_st[tid] == 1) {
-            q_next[tid] = (pos < q_du[tid]) ? A.ci[q_bu[tid] + pos] : INT_MAX;
+            q_next[tid] = (pos < q_du[tid]) ? A.hci[q_bu[tid] + pos] : INT_MAX;
             if (!exact) {
               if (cnt >= q_need[tid]) q_st[tid] = 2;
               else if (cnt + (q_du[tid] - pos) < q_need[tid]) q_st[tid] = 3;

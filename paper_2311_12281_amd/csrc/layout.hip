@@ -208,6 +208,46 @@ hipError_t exclusive_scan(hipStream_t s, const int64_t* in, int64_t* out, int64_
 
 }  // namespace
 
+hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
+                             const int32_t* h_ci, int32_t* d_hci) {
+  if (nnz <= 0 || n <= 0) return hipSuccess;
+  // rank: counting sort of the vertices by increasing degree, ties by id
+  int64_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, h_rp[v + 1] - h_rp[v]);
+  std::vector<int64_t> first((size_t)maxd + 2, 0);
+  for (int32_t v = 0; v < n; ++v) ++first[(size_t)(h_rp[v + 1] - h_rp[v])];
+  int64_t acc = 0;
+  for (auto& c : first) {
+    const int64_t t = c;
+    c = acc;
+    acc += t;
+  }
+  std::vector<int32_t> rank((size_t)n);
+  for (int32_t v = 0; v < n; ++v) rank[(size_t)v] = (int32_t)first[(size_t)(h_rp[v + 1] - h_rp[v])]++;
+  // renamed rows, each sorted again; threads take row ranges of about equal arc counts
+  std::vector<int32_t> out((size_t)nnz);
+  const int nth = 16;
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      // rows whose start lies in [nnz t / nth, nnz (t + 1) / nth): every row once
+      auto first_row = [&](int k) -> int32_t {
+        if (k >= nth) return n;
+        return (int32_t)(std::lower_bound(h_rp, h_rp + n, nnz * k / nth) - h_rp);
+      };
+      const int32_t r0 = first_row(t), r1 = first_row(t + 1);
+      for (int32_t v = r0; v < r1; ++v) {
+        int32_t* r = out.data() + h_rp[v];
+        for (int64_t k = h_rp[v]; k < h_rp[v + 1]; ++k) r[k - h_rp[v]] = rank[(size_t)h_ci[k]];
+        std::sort(r, r + (h_rp[v + 1] - h_rp[v]));
+      }
+    });
+  for (auto& x : th) x.join();
+  hipError_t e = hipMemcpyAsync(d_hci, out.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
                         const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
                         int2** d_edges_out, HubJob** d_jobs_out, LayoutResult* out) {

@@ -24,10 +24,12 @@
 
 namespace scan {
 
-uint64_t inmemory_footprint(int32_t n, int64_t nnz) {
+uint64_t inmemory_footprint(int32_t n, int64_t nnz, bool ranked) {
   const uint64_t m = (uint64_t)nnz / 2;
-  // row_ptr, col_idx, oriented edges, hub worklist, edge state, per-vertex state + outputs
-  return 8ull * ((uint64_t)n + 1) + 4ull * nnz + 8ull * m + 4ull * m + 1ull * m + 22ull * n + (1ull << 20);
+  // row_ptr, col_idx (and its ranked copy), oriented edges, hub worklist, edge
+  // state, per-vertex state + outputs
+  const uint64_t cols = (ranked && n > kHubBitmapBits) ? 8ull : 4ull;
+  return 8ull * ((uint64_t)n + 1) + cols * nnz + 8ull * m + 4ull * m + 1ull * m + 22ull * n + (1ull << 20);
 }
 
 namespace {
@@ -300,6 +302,7 @@ struct Streamer {
       lj = j;
     }
     A.ci = P.d_rows;
+    A.hci = P.d_rows;
     A.a_lo = lo_i;
     A.a_hi = hi_i;
     A.delta_a = P.h_rp[(size_t)lo_i];

@@ -88,6 +88,7 @@ struct HubJob {
 struct EdgeArgs {
   const int64_t* rp;
   const int32_t* ci;
+  const int32_t* hci;  // rows read by the LDS-hash kernel: ci, or ci renamed by degree rank
   const int2* edges;  // oriented: x = smaller side (deg, id), y = larger side
   int64_t e_begin, e_end;
   uint8_t* state;     // per oriented edge
@@ -170,5 +171,14 @@ struct LayoutResult {
 hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
                         const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
                         int2** d_edges, HubJob** d_jobs, LayoutResult* out);
+// Fills d_hci (nnz entries) with the rows of the CSR with every vertex renamed
+// to its rank in order of increasing degree (ties by id), each row sorted
+// again.  Intersection sizes do not depend on the names.  The top 2^20 ranks
+// hold most arc endpoints of a skewed graph, so the LDS-hash kernel covers
+// most of a long row with one bitmap window, and a survivor's low-degree
+// neighbours, the likely misses, come first, which settles dissimilar edges
+// earlier.  Built on the host threads and copied; synchronous.
+hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
+                             const int32_t* h_ci, int32_t* d_hci);
 
 }  // namespace scan

@@ -319,11 +319,16 @@ def spread_hub_graph(seed=11, heavy=400):
     return gg.from_edges(leaf, edges)
 
 
-def test_bitmap_and_hash_windows():
-    """The hub's row is taken as bitmap, hash, hash and bitmap windows."""
+@pytest.mark.parametrize("ranked", [False, True])
+def test_bitmap_and_hash_windows(ranked):
+    """With the rows as given the hub's row is taken as bitmap, hash, hash and
+    bitmap windows; with the rows renamed by degree rank (the graph has more
+    than 2^20 vertices) its neighbours move into a narrow id range."""
     g = spread_hub_graph()
-    check_graph(g, [((1, 12), 2), ((1, 16), 3), ((1, 25), 5), ((1, 40), 2)], "spread-hub")
-    check_graph(g, [((1, 16), 3)], "spread-hub-exhaustive", counts=False, pruning=False)
+    check_graph(g, [((1, 12), 2), ((1, 16), 3), ((1, 25), 5), ((1, 40), 2)], f"spread-hub-ranked{int(ranked)}",
+                hub_ranked=ranked)
+    check_graph(g, [((1, 16), 3)], f"spread-hub-ranked{int(ranked)}-exhaustive", counts=False, pruning=False,
+                hub_ranked=ranked)
 
 
 @pytest.mark.parametrize("name,gen", [
