@@ -464,7 +464,9 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 // both are full does it go on to the first bucket after its second one that
 // has room.  A probe reads both buckets at once; it has to look further only
 // when both are full and neither holds the element, which two-choice placement
-// at half load makes rare.  Slots of a bucket fill in order (each insert takes
+// at half load makes rare.  A window of at most kHubSparseMax elements places
+// first fit instead (first bucket, else second, else onwards), and a probe
+// reads the second bucket only when the first is full without the element.  Slots of a bucket fill in order (each insert takes
 // its first free slot), so a bucket is full exactly when its last slot is set,
 // and slots are never freed while a table is in use: a bucket that is not full
 // at probe time was not full when any later element was placed.
@@ -497,6 +499,19 @@ __device__ __forceinline__ void hub_insert(int32_t* table, int32_t x) {
   const bool second_first = bucket_free(T[b2]) > bucket_free(T[b1]);
   if (bucket_put(table, second_first ? b2 : b1, x)) return;
   if (bucket_put(table, second_first ? b1 : b2, x)) return;
+  uint32_t b = (b2 + 1) & (kHubBuckets - 1);
+  while (!bucket_put(table, b, x)) b = (b + 1) & (kHubBuckets - 1);
+}
+
+// First-fit placement for a sparse set (at most kHubSparseMax elements, a
+// quarter of the slots): the first bucket if it has room, else the second,
+// else the first bucket after the second with room.  A probe then needs the
+// second bucket only when the first is full, which at this load is rare.
+__device__ __forceinline__ void hub_insert_sparse(int32_t* table, int32_t x) {
+  uint32_t b1, b2;
+  hub_buckets(x, b1, b2);
+  if (bucket_put(table, b1, x)) return;
+  if (bucket_put(table, b2, x)) return;
   uint32_t b = (b2 + 1) & (kHubBuckets - 1);
   while (!bucket_put(table, b, x)) b = (b + 1) & (kHubBuckets - 1);
 }
@@ -542,9 +557,11 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* wsum
   return off + incl - x;
 }
 
-template <bool B>
+// Kinds of window: 0 hash set (two-choice), 1 bitmap, 2 sparse hash set
+// (first fit).
+template <int K>
 struct KindTag {
-  static constexpr bool value = B;
+  static constexpr int value = K;
 };
 
 // First index in (lo, hi) whose value is at least T in the ascending array
@@ -708,6 +725,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           }
         }
         const int32_t hi = (w1 < dv) ? A.hci[bv + w1] : INT_MAX;
+        const bool sparse = !bitmap && w1 - w0 <= kHubSparseMax;
         if (tid == 0) {
           s_min = INT_MAX;
           s_chunk = 0;
@@ -777,6 +795,8 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             if (bitmap) {
               const uint32_t off = (uint32_t)y[i] - (uint32_t)L;
               atomicOr(reinterpret_cast<uint32_t*>(table) + (off >> 5), 1u << (off & 31));
+            } else if (sparse) {
+              hub_insert_sparse(table, y[i]);
             } else {
               hub_insert(table, y[i]);
             }
@@ -791,7 +811,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         // group together.
         // the chunk loop, compiled once per kind of window
         auto chunk_loop = [&](auto kind) {
-        constexpr bool kBitmap = decltype(kind)::value;
+        constexpr int kKind = decltype(kind)::value;
         while (true) {
           // every lane adds 1, so a group's lanes receive 16 consecutive
           // values starting at a multiple of kHubGroup: value / kHubGroup is
@@ -836,7 +856,31 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
             }
             uint32_t step_hits = 0;
             const uint32_t step_seen = (uint32_t)min(max((left + kHubGroup - 1) / kHubGroup, 0), kHubUnroll);
-            if constexpr (kBitmap) {
+            if constexpr (kKind == 2) {
+              // first buckets only; the second one (and beyond) just for
+              // elements whose first bucket is full without them
+              int4 q[kHubUnroll];
+              uint32_t b2[kHubUnroll];
+#pragma unroll
+              for (int j = 0; j < kHubUnroll; ++j) {
+                uint32_t b1;
+                hub_buckets(x[j], b1, b2[j]);
+                q[j] = T4[b1];
+              }
+#pragma unroll
+              for (int j = 0; j < kHubUnroll; ++j) {
+                const uint32_t xj = (uint32_t)x[j];
+                const uint32_t dj = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
+                                        min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
+                bool h = dj == 0u;
+                if (!h && q[j].w >= 0) {  // first bucket full without x
+                  const int4 r = T4[b2[j]];
+                  h = bucket_has(r, x[j]);
+                  if (!h && r.w >= 0) h = hub_probe_tail(T4, x[j]);
+                }
+                step_hits += h ? 1u : 0u;
+              }
+            } else if constexpr (kKind == 1) {
               // ids outside L .. L + kHubBitmapBits - 1 (kHubNone included)
               // read the zero word just past the bitmap
               const uint32_t* bm = reinterpret_cast<const uint32_t*>(table);
@@ -905,8 +949,9 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
           if (exact) atomicAdd(&q_acc[k], ((unsigned long long)my_seen << 32) | my_hits);
         }
         };
-        if (bitmap) chunk_loop(KindTag<true>{});
-        else chunk_loop(KindTag<false>{});
+        if (bitmap) chunk_loop(KindTag<1>{});
+        else if (sparse) chunk_loop(KindTag<2>{});
+        else chunk_loop(KindTag<0>{});
         __syncthreads();
         if (tid < nbatch && q_st[tid] != 0 && q_next[tid] < hi) {
           // window finished for this survivor (or it was decided on the way)

@@ -79,6 +79,9 @@ constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill 
 // element on hold at least kHubBitmapMin elements of nbr(v).
 constexpr int kHubBitmapBits = kHubSlots * 32;
 constexpr int kHubBitmapMin = 4096;
+// A hash window of at most this many elements (a quarter of the slots) uses
+// first-fit placement, so that most probes read a single bucket.
+constexpr int kHubSparseMax = kHubSlots / 4;
 struct HubJob {
   int64_t begin;  // first edge of the job
   int32_t v;      // common larger side

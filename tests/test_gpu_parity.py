@@ -319,6 +319,39 @@ def spread_hub_graph(seed=11, heavy=400):
     return gg.from_edges(leaf, edges)
 
 
+def crowded_bucket_graph(seed=13, n=1 << 19, crowd=48, spread=700, heavy=300):
+    """Vertex 0 has a few hundred neighbours (one sparse hash window of the
+    LDS-hash kernel) of which `crowd` share the first bucket of the set's
+    multiplicative hash, so all but four of them are placed in their second
+    bucket (or beyond), and probes of ids hashing to the crowded bucket read
+    further than the first bucket.  Heavy neighbours link to many of these ids,
+    crowded ones included, so their edges to vertex 0 need the lookups."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(1, n, dtype=np.uint64)
+    b1 = ((x * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(19)
+    target = int(b1[rng.integers(len(b1))])
+    crowded = x[b1 == target][:crowd].astype(np.int64)
+    others = rng.choice(np.setdiff1d(np.arange(1, n), crowded), size=spread, replace=False)
+    hub_nbrs = np.unique(np.concatenate([crowded, others]))
+    edges = [(0, int(w)) for w in hub_nbrs]
+    for u in rng.choice(hub_nbrs, size=heavy, replace=False):
+        picks = np.unique(np.concatenate([rng.choice(crowded, size=crowd // 2, replace=False),
+                                          rng.choice(hub_nbrs, size=int(rng.integers(60, 200)), replace=False)]))
+        for w in picks:
+            if int(w) != int(u):
+                edges.append((int(u), int(w)))
+        # ids that hash to the crowded bucket but are not neighbours of vertex 0
+        for w in x[b1 == target][crowd:crowd + 8]:
+            edges.append((int(u), int(w)))
+    return gg.from_edges(n, edges)
+
+
+def test_crowded_hash_bucket():
+    g = crowded_bucket_graph()
+    check_graph(g, [((1, 4), 2), ((1, 3), 3), ((1, 6), 5), ((1, 10), 2)], "crowded-bucket")
+    check_graph(g, [((1, 4), 3)], "crowded-bucket-exhaustive", counts=False, pruning=False)
+
+
 @pytest.mark.parametrize("ranked", [False, True])
 def test_bitmap_and_hash_windows(ranked):
     """With the rows as given the hub's row is taken as bitmap, hash, hash and
