@@ -2,7 +2,7 @@
 // list of GPUSCAN++ Section 4.1 ("degree-oriented edge array": every edge
 // once as (u, v) with deg(u) < deg(v), or equal degrees and id(u) < id(v)),
 // grouped by the degree bucket of its smaller side and, inside a bucket, in
-// CSR order of the smaller side.  The grouping is a stable multi-way
+// CSR order of the larger side.  The grouping is a stable multi-way
 // partition: per-block bucket counts, one exclusive scan, ordered scatter.
 #include "scan_internal.h"
 
@@ -78,22 +78,20 @@ __global__ void k_check_arcs(int32_t n, int64_t nnz, const int64_t* rp, const in
 
 // Owner arc of each undirected edge, and its bucket (or -1 if arc i does not
 // own its edge).  With x = row of arc i and y = its neighbour, the edge's
-// smaller side by (degree, id) is u and the larger is v:
-//   buckets 0-5 (d_u <= 64, or d_v <= kHubMinDegree): owned by the arc in u's
-//     row, so these buckets list their edges grouped by the smaller side;
-//   bucket 6 (d_u > 64 and d_v > kHubMinDegree): owned by the arc in v's row,
-//     so the bucket lists its edges grouped by the larger side - each job of
-//     the LDS-hash kernel stages one larger list and streams the smaller
-//     lists of its in-edges.
+// smaller side by (degree, id) is u and the larger is v.  Every edge is owned
+// by the arc in v's row, so each bucket lists its edges grouped by the larger
+// side: consecutive edges share v's degree, role, bounds and row (the larger
+// list that the intersections search), and in bucket 6 each job of the
+// LDS-hash kernel stages one larger list and streams the smaller lists of its
+// in-edges.
 __device__ inline int arc_bucket(const int64_t* rp, const int32_t* ci, const int32_t* src, int64_t i) {
   const int32_t x = src[i], y = ci[i];
   const int64_t dx = rp[x + 1] - rp[x], dy = rp[y + 1] - rp[y];
   const bool x_smaller = dx < dy || (dx == dy && x < y);
-  if (x_smaller) {
-    const int b = bucket_of(dx);
-    return (b < 5 || dy <= kHubMinDegree) ? b : -1;
-  }
-  return (dy > 64 && dx > kHubMinDegree) ? 6 : -1;
+  const int64_t ds = x_smaller ? dx : dy, dl = x_smaller ? dy : dx;
+  int b = bucket_of(ds);
+  if (b == 5 && dl > kHubMinDegree) b = 6;
+  return x_smaller ? -1 : b;  // the larger side's arc owns the edge
 }
 
 __global__ __launch_bounds__(kBlock) void k_bucket_counts(int64_t nnz, const int64_t* rp,
@@ -138,8 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(int64_t nnz, const in
     if (b >= 0) {
       int64_t pos = running[b] + myrank;
       for (int w = 0; w < wave; ++w) pos += wave_cnt[b][w];
-      // stored as (smaller side, larger side)
-      edges[pos] = (b == kNumBuckets - 1) ? make_int2(ci[i], src[i]) : make_int2(src[i], ci[i]);
+      // stored as (smaller side, larger side); arc i lies in the larger side's row
+      edges[pos] = make_int2(ci[i], src[i]);
     }
     __syncthreads();
     if (threadIdx.x < kNumBuckets) {
