@@ -365,6 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
+  int32_t staged_v = -1;  // STAGE: the vertex whose list the wave's LDS slot holds
   for (int64_t base = A.e_begin + wave * 64; base < A.e_end; base += nwaves * 64) {
     const int64_t e = base + lane;
     EdgeView ev;
@@ -411,12 +412,17 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
         int verdict;
         if (STAGE && w.dv <= kHubMinDegree) {  // uniform over the wave (G = 64)
           int32_t* S = stage + (threadIdx.x >> 6) * kHubMinDegree;
-          // the wave's reads of the previous edge's copy come first
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          for (int64_t i = lane; i < w.dv; i += 64) S[i] = A.ci[w.bv + i];
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
+          // edges are grouped by the larger side, so consecutive edges of a
+          // wave mostly share it and its list is copied once
+          if (w.v != staged_v) {
+            // the wave's reads of the previous edge's copy come first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int64_t i = lane; i < w.dv; i += 64) S[i] = A.ci[w.bv + i];
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            staged_v = w.v;
+          }
           verdict = group_intersect<G>(A.ci + w.bu, w.du, S, w.dv, w.need - 2, exact, sub, gbase, gmask,
                                        cnt, consumed);
         } else {
