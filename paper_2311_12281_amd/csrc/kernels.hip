@@ -344,19 +344,103 @@ __device__ __forceinline__ T shfl_t(T x, int src) {
   return __shfl(x, src, 64);
 }
 
+// Per-wave LDS hash set for the staged bucket: kWaveSlots int32 slots in
+// buckets of 4, two-choice placement (the emptier of two buckets from one
+// multiplicative hash; both full: the first bucket after the second with
+// room), at most half full for a list of kHubMinDegree elements.  Empty slots
+// hold -1.  Slots of a bucket fill in order and are never freed while the set
+// is in use, so a bucket that is not full at probe time was not full when any
+// element was placed.
+constexpr int kWaveSlots = 2 * kHubMinDegree;
+constexpr int kWaveBuckets = kWaveSlots / 4;
+constexpr int kWaveBucketBits = 8;
+static_assert(kWaveBuckets == 1 << kWaveBucketBits, "bucket index width");
+
+__device__ __forceinline__ void wave_buckets(int32_t x, uint32_t& b1, uint32_t& b2) {
+  const uint32_t h = (uint32_t)x * 0x9E3779B1u;
+  b1 = h >> (32 - kWaveBucketBits);
+  b2 = ((h >> (32 - 2 * kWaveBucketBits)) ^ h) & (kWaveBuckets - 1);
+}
+
+__device__ __forceinline__ int wave_bucket_free(int4 q) {
+  return (q.x == -1) + (q.y == -1) + (q.z == -1) + (q.w == -1);
+}
+
+__device__ __forceinline__ bool wave_bucket_put(int32_t* T, uint32_t b, int32_t x) {
+  int32_t* slot = T + 4 * b;
+  if (atomicCAS(slot + 0, -1, x) == -1) return true;
+  if (atomicCAS(slot + 1, -1, x) == -1) return true;
+  if (atomicCAS(slot + 2, -1, x) == -1) return true;
+  return atomicCAS(slot + 3, -1, x) == -1;
+}
+
+__device__ __forceinline__ void wave_insert(int32_t* T, int32_t x) {
+  uint32_t b1, b2;
+  wave_buckets(x, b1, b2);
+  const int4* T4 = reinterpret_cast<const int4*>(T);
+  const bool second_first = wave_bucket_free(T4[b2]) > wave_bucket_free(T4[b1]);
+  if (wave_bucket_put(T, second_first ? b2 : b1, x)) return;
+  if (wave_bucket_put(T, second_first ? b1 : b2, x)) return;
+  uint32_t b = (b2 + 1) & (kWaveBuckets - 1);
+  while (!wave_bucket_put(T, b, x)) b = (b + 1) & (kWaveBuckets - 1);
+}
+
+__device__ __forceinline__ bool wave_has(const int32_t* T, int32_t x) {
+  uint32_t b1, b2;
+  wave_buckets(x, b1, b2);
+  const int4* T4 = reinterpret_cast<const int4*>(T);
+  const int4 q1 = T4[b1], q2 = T4[b2];
+  const auto has = [](int4 q, int32_t y) { return q.x == y || q.y == y || q.z == y || q.w == y; };
+  if (has(q1, x) || has(q2, x)) return true;
+  if ((q1.w | q2.w) < 0) return false;  // one of the two buckets has room
+  uint32_t b = (b2 + 1) & (kWaveBuckets - 1);
+  while (true) {
+    const int4 q = T4[b];
+    if (has(q, x)) return true;
+    if (q.w == -1) return false;
+    b = (b + 1) & (kWaveBuckets - 1);
+  }
+}
+
+// Staged-bucket intersection: the whole wave (64 lanes) probes the smaller
+// list, one element per lane per step, against the wave's hash set of the
+// larger list; the next step's elements are loaded while this one is probed.
+// Early exit as in group_intersect.
+__device__ __forceinline__ int wave_intersect(const int32_t* Arow, int64_t du, const int32_t* T,
+                                              int32_t need_open, bool exact, int lane, int32_t& cnt,
+                                              int64_t& consumed) {
+  cnt = 0;
+  consumed = 0;
+  int32_t xn = (lane < du) ? Arow[lane] : -1;
+  for (int64_t t = 0; t < du; t += 64) {
+    const int32_t x = xn;
+    const int64_t nx = t + 64 + lane;
+    xn = (nx < du) ? Arow[nx] : -1;
+    const bool f = (t + lane < du) && wave_has(T, x);
+    cnt += __popcll(__ballot(f));
+    const int64_t take = du - t < 64 ? du - t : 64;
+    consumed += take;
+    if (!exact) {
+      if (cnt >= need_open) return 2;
+      if (cnt + (du - (t + take)) < need_open) return 3;
+    }
+  }
+  return 1;
+}
+
 // Every lane classifies one edge of a chunk of 64 and applies the edges that
 // need no intersection; the edges that do are then taken 64/G at a time, one
 // per group of G lanes (the edge's fields are broadcast from the lane that
 // classified it).  Buckets 0-4 use G >= d_s (one tile); G = 64 also serves the
 // last bucket when it runs without the LDS-hash kernel.
 // STAGE (bucket 5, G = 64: both sides above 64 neighbours, the larger at most
-// kHubMinDegree): the wave first copies nbr(v) into its own LDS slot, so the
-// binary searches run in LDS instead of global memory.
+// kHubMinDegree): the wave loads nbr(v) into its own LDS hash set, and every
+// element of the smaller list is one hash probe.
 template <int MODE, int G, bool STAGE = false>
 __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
   static_assert(!STAGE || G == 64, "staging is per wave");
   if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
-  __shared__ int32_t stage[STAGE ? (kBlock / 64) * kHubMinDegree : 1];
+  __shared__ __align__(16) int32_t stage[STAGE ? (kBlock / 64) * kWaveSlots : 1];
   constexpr int kGroups = 64 / G;
   const int lane = threadIdx.x & 63;
   const int grp = lane / G, sub = lane & (G - 1), gbase = lane & ~(G - 1);
@@ -411,20 +495,27 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
         int64_t consumed;
         int verdict;
         if (STAGE && w.dv <= kHubMinDegree) {  // uniform over the wave (G = 64)
-          int32_t* S = stage + (threadIdx.x >> 6) * kHubMinDegree;
+          int32_t* T = stage + (threadIdx.x >> 6) * kWaveSlots;
           // edges are grouped by the larger side, so consecutive edges of a
-          // wave mostly share it and its list is copied once
+          // wave mostly share it and its set is built once
           if (w.v != staged_v) {
-            // the wave's reads of the previous edge's copy come first
+            // the wave's probes of the previous edge's set come first
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int64_t i = lane; i < w.dv; i += 64) S[i] = A.ci[w.bv + i];
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i < kWaveBuckets; i += 64) reinterpret_cast<int4*>(T)[i] = make_int4(-1, -1, -1, -1);
+            int32_t y[kHubMinDegree / 64];
+#pragma unroll
+            for (int k = 0; k < kHubMinDegree / 64; ++k) y[k] = (k * 64 + lane < w.dv) ? A.ci[w.bv + k * 64 + lane] : -1;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < kHubMinDegree / 64; ++k)
+              if (y[k] >= 0) wave_insert(T, y[k]);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             staged_v = w.v;
           }
-          verdict = group_intersect<G>(A.ci + w.bu, w.du, S, w.dv, w.need - 2, exact, sub, gbase, gmask,
-                                       cnt, consumed);
+          verdict = wave_intersect(A.ci + w.bu, w.du, T, w.need - 2, exact, lane, cnt, consumed);
         } else {
           verdict = group_intersect<G>(A.ci + w.bu, w.du, A.ci + w.bv, w.dv, w.need - 2, exact, sub, gbase,
                                        gmask, cnt, consumed);
