@@ -910,7 +910,7 @@ __global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* job
         auto chunk_loop = [&](auto kind) {
         constexpr int kKind = decltype(kind)::value;
         while (true) {
-          // every lane adds 1, so a group's lanes receive 16 consecutive
+          // every lane adds 1, so a group's lanes receive kHubGroup consecutive
           // values starting at a multiple of kHubGroup: value / kHubGroup is
           // the group's chunk (a uniform addend keeps this a single atomic per
           // wave and avoids any branch on the lane index)

@@ -64,7 +64,7 @@ constexpr int kHubBlock = 1024;    // threads per block of the LDS-hash kernel (
 constexpr int kHubBatch = 512;     // survivors per table fill
 constexpr int kHubPerThread = kHubJobEdges / kHubBlock;  // in-edges classified per thread and round
 constexpr int kHubInsertBatch = 4; // table inserts per thread with their loads issued together
-constexpr int kHubGroup = 16;      // lanes streaming one survivor
+constexpr int kHubGroup = 8;      // lanes streaming one survivor
 constexpr int kHubUnroll = 8;      // elements per lane per step
 constexpr int kHubChunk = 2048;    // elements of one survivor handed to a group at a time
 // col_idx is allocated with this many spare elements after its end, so that the
