@@ -75,7 +75,7 @@ typedef struct scan_opts {
                                    SCAN_UNCLASSIFIED (one more pass over the edges,
                                    Def 2.7 and Alg. 4); 0 (default): three roles */
   int32_t hub_ranked;           /* 1 (default): on the in-memory path, for graphs of more
-                                   than 2^20 vertices, the edges whose smaller side has
+                                   than 2^19 vertices, the edges whose smaller side has
                                    degree > 64 intersect a copy of the rows in which every
                                    vertex is renamed to its rank by increasing degree
                                    (4 more device bytes per arc, built on the host when the

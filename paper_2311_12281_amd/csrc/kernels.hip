@@ -687,7 +687,7 @@ __device__ __forceinline__ int64_t block_find(const int32_t* row, int64_t lo, in
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kHubBlock) void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs,
+__global__ __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(kHubWavesPerSimd, kHubWavesPerSimd))) void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs,
                                                    unsigned long long* counter, int32_t* wl) {
   constexpr int kGroups = kHubBlock / kHubGroup;
   constexpr int kStep = kHubGroup * kHubUnroll;  // elements per group step
@@ -1351,9 +1351,10 @@ int hub_grid_blocks() {
 void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, int64_t njobs,
                 unsigned long long* counter, int32_t* worklist) {
   if (njobs <= 0) return;
-  // one resident block per compute unit (the table fills most of its LDS);
+  // kHubBlocksPerCU resident blocks per compute unit (their tables fill most
+  // of its LDS; while one block waits at a barrier the other computes);
   // blocks take jobs from the counter until none are left
-  const unsigned grid = blocks_for(njobs, 1, hub_grid_blocks());
+  const unsigned grid = blocks_for(njobs, 1, (int64_t)kHubBlocksPerCU * hub_grid_blocks());
   switch (mode) {
     case MODE_CORES: k_hub<MODE_CORES><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;
     case MODE_MERGE: k_hub<MODE_MERGE><<<grid, kHubBlock, 0, s>>>(a, jobs, njobs, counter, worklist); break;

@@ -58,10 +58,12 @@ __host__ __device__ inline uint32_t closed_needed(uint64_t p, uint64_t q, uint64
 
 // LDS-hash kernel of the last bucket (d_u > 64): one job = up to kHubJobEdges
 // in-edges (u, v) of one larger side v, consecutive in the edge list.
-constexpr int kHubJobEdges = 4096; // in-edges per job
+constexpr int kHubJobEdges = 2048; // in-edges per job
 constexpr int64_t kHubJobWork = 1 << 24;  // smaller-list elements per job (bound on probes)
-constexpr int kHubBlock = 1024;    // threads per block of the LDS-hash kernel (one block per CU)
-constexpr int kHubBatch = 512;     // survivors per table fill
+constexpr int kHubBlock = 512;     // threads per block of the LDS-hash kernel
+constexpr int kHubBlocksPerCU = 2; // blocks resident per compute unit (each holds its own table)
+constexpr int kHubWavesPerSimd = kHubBlocksPerCU * kHubBlock / 256;  // 4 SIMDs of wave64 per CU
+constexpr int kHubBatch = 256;     // survivors per table fill
 constexpr int kHubPerThread = kHubJobEdges / kHubBlock;  // in-edges classified per thread and round
 constexpr int kHubInsertBatch = 4; // table inserts per thread with their loads issued together
 constexpr int kHubGroup = 8;      // lanes streaming one survivor
@@ -71,7 +73,7 @@ constexpr int kHubChunk = 2048;    // elements of one survivor handed to a group
 // LDS-hash kernel's step loads (up to two steps past a chunk's end, values
 // beyond the end ignored) need no clamping
 constexpr int64_t kColPad = 2 * kHubGroup * kHubUnroll;
-constexpr int kHubLog2Slots = 15;  // LDS hash table: 32768 int32 slots = 128 KiB
+constexpr int kHubLog2Slots = 14;  // LDS table per block: 16384 int32 slots = 64 KiB
 constexpr int kHubSlots = 1 << kHubLog2Slots;
 constexpr int kHubWindow = kHubSlots / 2;  // elements of nbr(v) per table fill (load <= 1/2)
 // The same LDS array read as a bitmap covers kHubBitmapBits consecutive ids;
@@ -176,11 +178,12 @@ hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_
                         int2** d_edges, HubJob** d_jobs, LayoutResult* out);
 // Fills d_hci (nnz entries) with the rows of the CSR with every vertex renamed
 // to its rank in order of increasing degree (ties by id), each row sorted
-// again.  Intersection sizes do not depend on the names.  The top 2^20 ranks
-// hold most arc endpoints of a skewed graph, so the LDS-hash kernel covers
-// most of a long row with one bitmap window, and a survivor's low-degree
-// neighbours, the likely misses, come first, which settles dissimilar edges
-// earlier.  Built on the host threads and copied; synchronous.
+// again.  Intersection sizes do not depend on the names.  The top
+// kHubBitmapBits ranks hold most arc endpoints of a skewed graph, so the
+// LDS-hash kernel covers most of a long row with one bitmap window, and a
+// survivor's low-degree neighbours, the likely misses, come first, which
+// settles dissimilar edges earlier.  Built on the host threads and copied;
+// synchronous.
 hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
                              const int32_t* h_ci, int32_t* d_hci);
 

@@ -295,10 +295,10 @@ def test_full_survivor_batch():
 def spread_hub_graph(seed=11, heavy=400):
     """Vertex 0 has a neighbourhood whose ids are dense in some ranges and
     sparse in others, so the LDS-hash kernel takes it as a bitmap window
-    (ids 1 .. 9000 and 2^20, the last bit of that window's id range), two
-    hash windows (33000 ids spread over 2^24 ids from 2^21 on, about 2000 per
-    2^20 ids) and a bitmap window again (the last spread ids with 6000
-    consecutive ids just after them).  Heavy neighbours of vertex 0 get
+    (ids 1 .. 9000), hash windows (2^20, 2^20 + 1 and 33000 ids spread over
+    2^24 ids from 2^21 on, a few hundred per bitmap's worth of ids) and a
+    bitmap window again (the last spread ids with 6000 consecutive ids just
+    after them).  Heavy neighbours of vertex 0 get
     100 .. 300 more neighbours inside its neighbourhood and 0 .. 200 private
     leaves, so their edges to the hub have a smaller side of degree > 64,
     span every window and range from similar to dissimilar."""
@@ -354,9 +354,9 @@ def test_crowded_hash_bucket():
 
 @pytest.mark.parametrize("ranked", [False, True])
 def test_bitmap_and_hash_windows(ranked):
-    """With the rows as given the hub's row is taken as bitmap, hash, hash and
-    bitmap windows; with the rows renamed by degree rank (the graph has more
-    than 2^20 vertices) its neighbours move into a narrow id range."""
+    """With the rows as given the hub's row is taken as bitmap, hash and
+    bitmap windows; with the rows renamed by degree rank (the graph is large
+    enough for the renaming) its neighbours move into a narrow id range."""
     g = spread_hub_graph()
     check_graph(g, [((1, 12), 2), ((1, 16), 3), ((1, 25), 5), ((1, 40), 2)], f"spread-hub-ranked{int(ranked)}",
                 hub_ranked=ranked)
