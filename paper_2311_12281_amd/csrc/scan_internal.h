@@ -68,7 +68,7 @@ constexpr int kHubPerThread = kHubJobEdges / kHubBlock;  // in-edges classified 
 constexpr int kHubInsertBatch = 4; // table inserts per thread with their loads issued together
 constexpr int kHubGroup = 8;      // lanes streaming one survivor
 constexpr int kHubUnroll = 8;      // elements per lane per step
-constexpr int kHubChunk = 2048;    // elements of one survivor handed to a group at a time
+constexpr int kHubChunk = 1024;    // elements of one survivor handed to a group at a time
 // col_idx is allocated with this many spare elements after its end, so that the
 // LDS-hash kernel's step loads (up to two steps past a chunk's end, values
 // beyond the end ignored) need no clamping
