@@ -25,6 +25,7 @@ def check_symbols(names):
     assert "gfx950" in S.scan_version()
     o = S.scan_opts_default()
     assert o.validate == 1 and o.pruning == 1 and o.timing == 0 and o.device_budget_bytes == 0
+    assert o.hub_ranked == 1 and o.hub_outlier == 0 and o.strategy == 0 and not o.hip_stream
 
 
 def check_threshold():

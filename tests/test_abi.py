@@ -66,3 +66,36 @@ def test_binding_never_imports_the_oracle_or_torch():
     src = open(os.path.join(ROOT, "paper_2311_12281_amd", "__init__.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
     assert "import torch" not in src
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes mirrors of the public structs have the header's size and
+    field offsets (gcc compiles a probe of the header; no library is loaded)."""
+    import ctypes
+    sys.path.insert(0, ROOT)
+    import paper_2311_12281_amd as S
+    structs = {"scan_opts": S.scan_opts, "scan_stats": S.scan_stats, "scan_batch": S.scan_batch}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "scan.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+    # and the same fields, in the same order, as the header declares
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for name, cls in structs.items():
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+        fields = re.findall(r"([A-Za-z_][A-Za-z_0-9]*)\s*(?:\[[^\]]*\])?\s*;", body)
+        assert fields == [f for f, _ in cls._fields_], (name, fields)
