@@ -33,6 +33,22 @@ def test_batch_matches_oracle_per_graph():
             assert_same(l, r, ol, orr, f"graph {k} eps={p}/{q} mu={mu}")
 
 
+def test_batch_large_enough_for_ranked_rows():
+    """A batch of 70 R-MAT scale-13 graphs: the disjoint union has more than
+    2^19 vertices, so the LDS-hash kernel reads the degree-ranked copy of the
+    rows of the union, and the graphs have hubs for it to work on."""
+    graphs = [gg.rmat(13, 16, seed=100 + k) for k in range(70)]
+    assert sum(g.n for g in graphs) > (1 << 19)
+    eps = [(1, 2 + k % 9) for k in range(70)]
+    mus = [2 + k % 7 for k in range(70)]
+    note("batch above 2^19 vertices")
+    with S.Batch(graphs, eps, mus) as B:
+        labels, roles = B.run(replay=True)
+        for k, (g, (p, q), mu, l, r) in enumerate(zip(graphs, eps, mus, B.split(labels), B.split(roles))):
+            ol, orr = oracle.scan(g, p, q, mu)
+            assert_same(l, r, ol, orr, f"graph {k} eps={p}/{q} mu={mu}")
+
+
 def test_batch_replays_match_eager():
     graphs, eps, mus = _batch(80, seed=5)
     note("batch replay vs eager")
