@@ -433,9 +433,10 @@ __device__ __forceinline__ int wave_intersect(const int32_t* Arow, int64_t du, c
 // per group of G lanes (the edge's fields are broadcast from the lane that
 // classified it).  Buckets 0-4 use G >= d_s (one tile); G = 64 also serves the
 // last bucket when it runs without the LDS-hash kernel.
-// STAGE (bucket 5, G = 64: both sides above 64 neighbours, the larger at most
-// kHubMinDegree): the wave loads nbr(v) into its own LDS hash set, and every
-// element of the smaller list is one hash probe.
+// STAGE (buckets 4 and 5, G = 64): for an edge whose larger side has at most
+// kHubMinDegree neighbours, the wave loads nbr(v) into its own LDS hash set,
+// and every element of the smaller list is one hash probe; edges with a
+// larger side above that search nbr(v) in global memory.
 template <int MODE, int G, bool STAGE = false>
 __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
   static_assert(!STAGE || G == 64, "staging is per wave");
@@ -1284,6 +1285,7 @@ void launch_edges_mode(hipStream_t s, int bucket, const EdgeArgs& a) {
     case 1: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
     case 2: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
     case 3: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
+    case 4:
     case 5: k_group<MODE, 64, true><<<grid, kBlock, 0, s>>>(a); break;
     default: k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a); break;
   }
@@ -1311,7 +1313,7 @@ void launch_edges_width(hipStream_t s, int lanes, const EdgeArgs& a) {
     case 16: k_group<MODE, 16><<<grid, kBlock, 0, s>>>(a); break;
     case 32: k_group<MODE, 32><<<grid, kBlock, 0, s>>>(a); break;
     default:
-      if (a.bucket == 5) k_group<MODE, 64, true><<<grid, kBlock, 0, s>>>(a);
+      if (a.bucket == 4 || a.bucket == 5) k_group<MODE, 64, true><<<grid, kBlock, 0, s>>>(a);
       else k_group<MODE, 64><<<grid, kBlock, 0, s>>>(a);
       break;
   }
