@@ -254,6 +254,15 @@ def test_stats_are_consistent():
         assert st["evaluated"]["cores"] + st["bounded"]["cores"] <= g.m
 
 
+@pytest.mark.parametrize("ranked", [False, True])
+def test_rmat20_permuted(ranked):
+    """R-MAT scale 20 with shuffled ids (no correlation between id and degree),
+    above the size at which the LDS-hash kernel reads degree-ranked rows: the
+    same counts and clusterings with and without them."""
+    g, _ = gg.permute(gg.rmat(20, 16, seed=4), 7)
+    check_graph(g, [((1, 5), 5), ((1, 2), 3), ((4, 5), 2)], f"rmat20-permuted-ranked{int(ranked)}", hub_ranked=ranked)
+
+
 @pytest.mark.skipif(os.environ.get("SCAN_SKIP_FULL") == "1", reason="full-size case disabled")
 def test_rmat22_full_size():
     """R-MAT scale 22, edge factor 16: every arc count and every label/role at
