@@ -708,6 +708,10 @@ __global__ __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(kHubW
   __shared__ int64_t wsum[kHubBlock / 64];
   __shared__ int64_t s_job;
   __shared__ int32_t s_n, s_min, s_chunk, s_first;
+  // the job's windows found so far (every batch of a job has the same ones):
+  // window k is elements s_wend[k - 1] .. s_wend[k] - 1 of nbr(v) (s_wend[-1] = 0)
+  __shared__ int64_t s_wend[kHubMaxWindows];
+  __shared__ uint8_t s_wbitmap[kHubMaxWindows];
   // cores pass: similar verdicts of this job's edges on the common larger side
   // v, added to v's lower bound once per job (all of a job's edges would
   // otherwise update the same counter one by one); v's degree is above
@@ -790,6 +794,7 @@ __global__ __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(kHubW
       const int64_t ws = ((int64_t)A.hci[bv] >= T) ? 0 : block_find(A.hci + bv, 0, dv, T, &s_first);
       if (dv - ws >= kHubBitmapMin) wsuf = ws;
     }
+    int32_t n_known = 0;  // windows of this job in s_wend / s_wbitmap
     // Phase B
     for (int32_t b0 = 0; b0 < S; b0 += kHubBatch) {
       const int32_t nbatch = (S - b0 < kHubBatch) ? S - b0 : kHubBatch;
@@ -806,20 +811,36 @@ __global__ __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(kHubW
         q_next[tid] = (keep && ev.du > 0) ? A.hci[ev.bu] : INT_MAX;
         q_st[tid] = keep ? 1 : 0;
       }
-      for (int64_t w0 = 0, w1 = 0; w0 < dv; w0 = w1) {
+      int32_t wi = 0;
+      for (int64_t w0 = 0, w1 = 0; w0 < dv; w0 = w1, ++wi) {
         // This window is a bitmap of the ids L .. L + kHubBitmapBits - 1 if
         // that range holds at least kHubBitmapMin elements of nbr(v) from w0
         // on, else a hash set of the next kHubWindow elements (at most up to
-        // the bitmap suffix).
+        // the bitmap suffix).  A window an earlier batch of the job found is
+        // taken from LDS.
         const int32_t L = A.hci[bv + w0];
         bool bitmap = false;
-        w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
-        if (w0 < wsuf && w1 > wsuf) w1 = wsuf;
-        if (dv - w0 >= kHubBitmapMin) {
-          const int64_t wb = block_find(A.hci + bv, w0, dv, (int64_t)L + kHubBitmapBits, &s_first);
-          if (wb - w0 >= kHubBitmapMin) {
-            bitmap = true;
-            w1 = wb;
+        if (wi < n_known) {
+          w1 = s_wend[wi];
+          bitmap = s_wbitmap[wi] != 0;
+        } else {
+          w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+          if (w0 < wsuf && w1 > wsuf) w1 = wsuf;
+          if (dv - w0 >= kHubBitmapMin) {
+            const int64_t wb = block_find(A.hci + bv, w0, dv, (int64_t)L + kHubBitmapBits, &s_first);
+            if (wb - w0 >= kHubBitmapMin) {
+              bitmap = true;
+              w1 = wb;
+            }
+          }
+          if (wi < kHubMaxWindows) {
+            // every thread found the same window; the first records it (read
+            // by the next batch, after the barriers below)
+            if (tid == 0) {
+              s_wend[wi] = w1;
+              s_wbitmap[wi] = bitmap ? 1 : 0;
+            }
+            n_known = wi + 1;
           }
         }
         const int32_t hi = (w1 < dv) ? A.hci[bv + w1] : INT_MAX;

@@ -84,6 +84,8 @@ constexpr int kHubBitmapMin = 4096;
 // A hash window of at most this many elements (a quarter of the slots) uses
 // first-fit placement, so that most probes read a single bucket.
 constexpr int kHubSparseMax = kHubSlots / 4;
+// windows of a job that its later batches take from LDS instead of finding again
+constexpr int kHubMaxWindows = 64;
 struct HubJob {
   int64_t begin;  // first edge of the job
   int32_t v;      // common larger side
