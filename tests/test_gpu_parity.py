@@ -361,6 +361,34 @@ def test_crowded_hash_bucket():
     check_graph(g, [((1, 4), 3)], "crowded-bucket-exhaustive", counts=False, pruning=False)
 
 
+def bitmap_edge_graph(seed=17, bits=1 << 19, heavy=200):
+    """Vertex 0's row is 6000 consecutive ids from 1 on plus the ids 1 + bits - 1
+    (the last id a bitmap window starting at id 1 covers) and 1 + bits (the
+    first it does not), so the row is a bitmap window followed by a short hash
+    window.  Heavy neighbours link to both boundary ids, to ids just past them
+    that are not in the row, and to many row ids, so probes hit every edge of
+    the bitmap's id range."""
+    rng = np.random.default_rng(seed)
+    last, first_out = 1 + bits - 1, 1 + bits
+    hub_nbrs = np.concatenate([np.arange(1, 6001), [last, first_out]])
+    n = first_out + 8
+    edges = [(0, int(w)) for w in hub_nbrs]
+    for u in rng.choice(np.arange(1, 6001), size=heavy, replace=False):
+        picks = set(int(w) for w in rng.choice(hub_nbrs, size=int(rng.integers(80, 200)), replace=False))
+        picks |= {last, first_out, first_out + 1, first_out + 2, 6001}
+        picks.discard(int(u))
+        edges += [(int(u), w) for w in sorted(picks)]
+    return gg.from_edges(n, edges)
+
+
+@pytest.mark.parametrize("ranked", [False, True])
+def test_bitmap_window_edges(ranked):
+    g = bitmap_edge_graph()
+    check_graph(g, [((1, 8), 2), ((1, 5), 3), ((1, 12), 4)], f"bitmap-edge-ranked{int(ranked)}", hub_ranked=ranked)
+    check_graph(g, [((1, 8), 3)], f"bitmap-edge-ranked{int(ranked)}-exhaustive", counts=False, pruning=False,
+                hub_ranked=ranked)
+
+
 @pytest.mark.parametrize("ranked", [False, True])
 def test_bitmap_and_hash_windows(ranked):
     """With the rows as given the hub's row is taken as bitmap, hash and
