@@ -503,10 +503,12 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
             // the wave's probes of the previous edge's set come first
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < kWaveBuckets; i += 64) reinterpret_cast<int4*>(T)[i] = make_int4(-1, -1, -1, -1);
+            for (int i = lane; i < kWaveBuckets; i += 64)
+              reinterpret_cast<int4*>(T)[i] = make_int4(-1, -1, -1, -1);
             int32_t y[kHubMinDegree / 64];
 #pragma unroll
-            for (int k = 0; k < kHubMinDegree / 64; ++k) y[k] = (k * 64 + lane < w.dv) ? A.ci[w.bv + k * 64 + lane] : -1;
+            for (int k = 0; k < kHubMinDegree / 64; ++k)
+              y[k] = (k * 64 + lane < w.dv) ? A.ci[w.bv + k * 64 + lane] : -1;
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -553,9 +555,10 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 //            test); otherwise it is the next kHubWindow elements, kept as a
 //            hash set, cut short where the longest suffix of nbr(v) that one
 //            bitmap covers begins.  A survivor stops as soon as its verdict
-//            is certain.  The rows may be given with vertices renamed by
-//            degree rank (A.hci), which packs most of a long row into the
-//            last bitmap window.
+//            is certain.  The windows that the first batch of a job finds are
+//            kept in LDS for its later batches.  The rows may be given with
+//            vertices renamed by degree rank (A.hci), which packs most of a
+//            long row into the last bitmap window.
 // LDS hash set: kHubSlots int32 slots viewed as buckets of 4 (one 16-byte
 // LDS load each).  Two-choice placement: every element has two buckets, both
 // derived from one multiplicative hash, and goes to the emptier one; only when
@@ -564,10 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
 // when both are full and neither holds the element, which two-choice placement
 // at half load makes rare.  A window of at most kHubSparseMax elements places
 // first fit instead (first bucket, else second, else onwards), and a probe
-// reads the second bucket only when the first is full without the element.  Slots of a bucket fill in order (each insert takes
-// its first free slot), so a bucket is full exactly when its last slot is set,
-// and slots are never freed while a table is in use: a bucket that is not full
-// at probe time was not full when any later element was placed.
+// reads the second bucket only when the first is full without the element.
+// Slots of a bucket fill in order (each insert takes its first free slot), so
+// a bucket is full exactly when its last slot is set, and slots are never
+// freed while a table is in use: a bucket that is not full at probe time was
+// not full when any later element was placed.
 constexpr int kHubBucketBits = kHubLog2Slots - 2;
 constexpr int kHubBuckets = 1 << kHubBucketBits;
 static_assert(2 * kHubBucketBits <= 32, "both bucket indices come from one 32-bit product");
@@ -688,8 +692,9 @@ __device__ __forceinline__ int64_t block_find(const int32_t* row, int64_t lo, in
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(kHubWavesPerSimd, kHubWavesPerSimd))) void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs,
-                                                   unsigned long long* counter, int32_t* wl) {
+__global__ __launch_bounds__(kHubBlock)
+__attribute__((amdgpu_waves_per_eu(kHubWavesPerSimd, kHubWavesPerSimd)))  // kHubBlocksPerCU blocks fit
+void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* counter, int32_t* wl) {
   constexpr int kGroups = kHubBlock / kHubGroup;
   constexpr int kStep = kHubGroup * kHubUnroll;  // elements per group step
   // hash set, or bitmap plus one zero word that out-of-range probes read
