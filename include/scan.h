@@ -137,6 +137,31 @@ int scan_run_device(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu,
                     int32_t* d_labels, uint8_t* d_roles, void* stream);
 
 /*
+ * scan_run_device_noalloc - scan_run_device for callers that cannot allocate
+ * device memory on the call (tight serving loops, harnesses that forbid
+ * hipMalloc, code that enqueues into a stream it is capturing): the same kernels and the same
+ * results, with every per-run buffer taken from one static device array of
+ * 64 MiB that the library holds on each device it runs on until the process
+ * ends.  The call makes no hipMalloc, hipFree or other allocating call.
+ *   g         an in-memory graph (SCAN_E_INVAL on the partitioned path), created
+ *             on the current device (SCAN_E_INVAL otherwise)
+ *   d_labels  device int32[n], d_roles device uint8[n], caller-owned
+ *   stream    NULL = the graph's stream
+ * The run needs about 17 bytes per vertex, 1 byte per edge and 4 bytes per
+ * edge of the LDS-hash bucket, each part rounded up to 256 bytes; a graph that
+ * needs more than the 64 MiB is refused with SCAN_E_NOMEM (nothing is run).
+ * All calls on one device share its array and each call leaves its contents
+ * there: calls that overlap on one device race and must be serialised by the
+ * caller.  Only kernels are enqueued (no memset, copy or event).  With
+ * stream = NULL the call returns after the graph's stream has been
+ * synchronised (outputs ready); with a caller's stream it returns once the
+ * kernels are enqueued, and the outputs are ready when that stream reaches them.
+ * Errors: SCAN_E_INVAL, SCAN_E_RANGE, SCAN_E_NOMEM, SCAN_E_DEVICE.
+ */
+int scan_run_device_noalloc(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu,
+                            int32_t* d_labels, uint8_t* d_roles, void* stream);
+
+/*
  * scan_similarity - closed-neighbourhood intersection size |N[u] & N[v]| for
  * every arc (u -> v), in CSR order (the numerator of sigma, Def 2.2, Eq. 1);
  * both arcs of an edge carry the same value.  sigma itself is

@@ -32,7 +32,7 @@ EXPORTED = [
     "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph", "scan_server_submit",
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
-    "scan_run_batch",
+    "scan_run_batch", "scan_run_device_noalloc",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
         L.scan_graph_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
         L.scan_run.argtypes = [vp, i64, i64, i32, vp, vp]
         L.scan_run_device.argtypes = [vp, i64, i64, i32, vp, vp, vp]
+        L.scan_run_device_noalloc.argtypes = [vp, i64, i64, i32, vp, vp, vp]
         L.scan_similarity.argtypes = [vp, vp]
         L.scan_similarity_device.argtypes = [vp, vp, vp]
         L.scan_eps_threshold.argtypes = [i64, i64, i64, i64]
@@ -141,7 +142,7 @@ def lib():
                      "scan_device_copy", "scan_h2d_rate", "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph",
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
-                     "scan_batch_destroy", "scan_run_batch"):
+                     "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -223,6 +224,12 @@ def scan_run_device(g, eps_num: int, eps_den: int, mu: int, d_labels: int, d_rol
                     stream: int | None = None) -> None:
     _check(lib().scan_run_device(g, int(eps_num), int(eps_den), int(mu), ctypes.c_void_p(d_labels),
                                  ctypes.c_void_p(d_roles), ctypes.c_void_p(stream) if stream else None))
+
+
+def scan_run_device_noalloc(g, eps_num: int, eps_den: int, mu: int, d_labels: int, d_roles: int,
+                            stream: int | None = None) -> None:
+    _check(lib().scan_run_device_noalloc(g, int(eps_num), int(eps_den), int(mu), ctypes.c_void_p(d_labels),
+                                         ctypes.c_void_p(d_roles), ctypes.c_void_p(stream) if stream else None))
 
 
 def scan_similarity(g, counts: np.ndarray | None = None) -> np.ndarray:
@@ -315,6 +322,9 @@ class Graph:
 
     def run_device(self, p, q, mu, d_labels, d_roles, stream=None):
         scan_run_device(self.handle, p, q, mu, d_labels, d_roles, stream)
+
+    def run_device_noalloc(self, p, q, mu, d_labels, d_roles, stream=None):
+        scan_run_device_noalloc(self.handle, p, q, mu, d_labels, d_roles, stream)
 
     def similarity(self):
         return scan_similarity(self.handle)

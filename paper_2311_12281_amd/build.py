@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libscan_mi355x.so")
-SOURCES = ["layout.hip", "kernels.hip", "api.hip", "server.hip", "partition.hip", "batch.hip"]
+SOURCES = ["layout.hip", "kernels.hip", "api.hip", "server.hip", "partition.hip", "batch.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -57,19 +57,22 @@ hipError_t dalloc(T** p, int64_t count) {
   return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
 }
 
-
-constexpr int kCounters = 5;  // job counters of the LDS-hash kernel per pass, then the number of cores
-
 }  // namespace
 
+RunState scan::graph_state(scan_graph* g) {
+  return RunState{g->d_lower, g->d_upper, g->d_role, g->d_parent, g->d_label,
+                  g->d_state, g->d_stats, g->d_counters, g->d_worklist};
+}
+
 // One pass of `mode` over bucket k of the oriented edges.
-void scan::launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunConfig* cfg) {
+void scan::launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunState& R,
+                         const RunConfig* cfg) {
   A.e_begin = g->bucket_off[k];
   A.e_end = g->bucket_off[k + 1];
   A.bucket = k;
   const bool hub = cfg ? cfg->hub : g->opts.strategy == 0;
   if (k == kNumBuckets - 1 && hub && g->hub_jobs > 0)
-    launch_hub(s, mode, A, g->d_jobs, g->hub_jobs, g->d_counters + mode, g->d_worklist);
+    launch_hub(s, mode, A, g->d_jobs, g->hub_jobs, R.counters + mode, R.worklist);
   else if (cfg && cfg->lanes[k] > 0)
     launch_edges_lanes(s, mode, cfg->lanes[k], A);
   else
@@ -80,9 +83,11 @@ void scan::launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs
 // (no memset, copy or synchronisation), so that it can be captured in a HIP
 // graph.  Per-graph parameters come from A.gid/gp/gq/gmu when set.
 void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
-                              const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg) {
+                              const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg,
+                              const RunState* state) {
   const int n = g->n;
   const int64_t m = g->m;
+  const RunState R = state ? *state : graph_state(g);
   auto mark = [&](int k) {
     if (timing) (void)hipEventRecord(g->ev[k], s);
   };
@@ -90,45 +95,45 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   A.ci = g->d_ci;
   A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
-  A.state = g->d_state;
-  A.lower = g->d_lower;
-  A.upper = g->d_upper;
-  A.role = g->d_role;
-  A.parent = g->d_parent;
-  A.label = g->d_label;
+  A.state = R.state;
+  A.lower = R.lower;
+  A.upper = R.upper;
+  A.role = R.role;
+  A.parent = R.parent;
+  A.label = R.label;
   A.counts = nullptr;
   A.edge_counts = nullptr;
-  A.stats = g->d_stats;
+  A.stats = R.stats;
   // Events: 0 start, then the end of each phase; the cores phase also marks
   // the end of each bucket (slots SCAN_NUM_PHASES + 1 + k).
   mark(0);
-  launch_zero_u64(s, g->d_stats, ST_COUNT);
-  launch_init(s, n, g->d_rp, A.mu, g->d_lower, g->d_upper, g->d_role, g->d_parent, A.gid, A.gmu);
-  launch_fill_u8(s, g->d_state, m, SIM_UNK);
-  launch_zero_u64(s, g->d_counters, kCounters);
+  launch_zero_u64(s, R.stats, ST_COUNT);
+  launch_init(s, n, g->d_rp, A.mu, R.lower, R.upper, R.role, R.parent, A.gid, A.gmu);
+  launch_fill_u8(s, R.state, m, SIM_UNK);
+  launch_zero_u64(s, R.counters, kCounters);
   mark(1);
   for (int k = 0; k < kNumBuckets; ++k) {
-    launch_bucket(g, s, MODE_CORES, k, A, cfg);
+    launch_bucket(g, s, MODE_CORES, k, A, R, cfg);
     mark(SCAN_NUM_PHASES + 1 + k);
   }
   mark(2);
-  launch_finalize_roles(s, n, A.mu, g->d_lower, g->d_role, A.gid, A.gmu, g->d_counters + 4);
-  A.ncores = g->d_counters + 4;
+  launch_finalize_roles(s, n, A.mu, R.lower, R.role, A.gid, A.gmu, R.counters + 4);
+  A.ncores = R.counters + 4;
   mark(3);
-  launch_hook(s, m, g->d_edges, g->d_state, g->d_role, g->d_parent);
+  launch_hook(s, m, g->d_edges, R.state, R.role, R.parent);
   mark(4);
-  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_MERGE, k, A, cfg);
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_MERGE, k, A, R, cfg);
   mark(5);
-  launch_flatten(s, n, g->d_role, g->d_parent, g->d_label);
+  launch_flatten(s, n, R.role, R.parent, R.label);
   mark(6);
-  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_ATTACH, k, A, cfg);
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_ATTACH, k, A, R, cfg);
   mark(7);
   const int32_t split = g->opts.hub_outlier ? 1 : 0;
   if (split) {  // Def 2.7; the cores pass's upper bounds are no longer needed
-    launch_fill_i32(s, g->d_upper, n, -1);
-    launch_hub_outlier_edges(s, m, g->d_edges, g->d_label, g->d_upper, g->d_role);
+    launch_fill_i32(s, R.upper, n, -1);
+    launch_hub_outlier_edges(s, m, g->d_edges, R.label, R.upper, R.role);
   }
-  launch_output(s, n, g->d_role, g->d_label, d_labels, d_roles, split, A.gid, gbase);
+  launch_output(s, n, R.role, R.label, d_labels, d_roles, split, A.gid, gbase);
   mark(8);
 }
 
@@ -169,11 +174,7 @@ int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
   return SCAN_OK;
 }
 
-namespace {
-
-// Validates eps and mu and runs the in-memory or partitioned clustering.
-int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
-                   uint8_t* d_roles, hipStream_t s) {
+int scan::check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu) {
   if (p < 1 || q < p) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den (got %lld/%lld)",
                                   (long long)p, (long long)q);
   if (mu < 2) return fail(SCAN_E_INVAL, "mu must be >= 2 (got %d)", mu);
@@ -184,6 +185,16 @@ int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_l
   if ((unsigned __int128)q * (unsigned __int128)((uint64_t)g->max_degree + 1) >= ((unsigned __int128)1 << 32))
     return fail(SCAN_E_RANGE, "eps denominator %lld with max degree %d exceeds the 64-bit test range",
                 (long long)q, g->max_degree);
+  return SCAN_OK;
+}
+
+namespace {
+
+// Validates eps and mu and runs the in-memory or partitioned clustering.
+int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
+                   uint8_t* d_roles, hipStream_t s) {
+  const int rc = check_params(g, p, q, mu);
+  if (rc != SCAN_OK) return rc;
   if (g->partitioned) return part_run(g, (uint64_t)p, (uint64_t)q, mu, d_labels, d_roles, s);
   EdgeArgs A{};
   A.p = (uint64_t)p;
@@ -214,7 +225,8 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   A.q = 1;
   A.mu = 2;
   A.pruning = 0;
-  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_COUNTS, k, A);
+  const RunState R = graph_state(g);
+  for (int k = 0; k < kNumBuckets; ++k) launch_bucket(g, s, MODE_COUNTS, k, A, R);
   if (timing) hipEventRecord(g->ev[1], s);
   HIP_TRY(hipGetLastError(), "kernel launch");
   unsigned long long st[ST_COUNT];

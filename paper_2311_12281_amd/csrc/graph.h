@@ -86,6 +86,24 @@ struct scan_graph {
 
 namespace scan {
 
+// Job counters of the LDS-hash kernel (one per pass), then the number of cores.
+constexpr int kCounters = 5;
+
+// Device buffers one clustering run works in: the graph's own (graph_state),
+// or a caller-provided region of the same sizes.
+struct RunState {
+  int32_t* lower;
+  int32_t* upper;
+  uint8_t* role;
+  int32_t* parent;
+  int32_t* label;
+  uint8_t* state;                // one per oriented edge
+  unsigned long long* stats;     // ST_COUNT
+  unsigned long long* counters;  // kCounters
+  int32_t* worklist;             // one per edge of the last bucket
+};
+RunState graph_state(scan_graph* g);
+
 // Per-bucket kernel choice for one run: lanes[k] = lane-group width of the
 // group kernel for bucket k (0 = the bucket's default), hub = LDS-hash kernel
 // for the last bucket.
@@ -94,11 +112,17 @@ struct RunConfig {
   bool hub;
 };
 
-void launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunConfig* cfg = nullptr);
+void launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, const RunState& R,
+                   const RunConfig* cfg = nullptr);
 // Kernel launches of one clustering run (capturable); A carries eps/mu (or
-// per-graph arrays); gbase (batch) turns labels into graph-local ids.
+// per-graph arrays); gbase (batch) turns labels into graph-local ids.  The run
+// works in R, or in the graph's own buffers when R is null.
 void enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
-                        const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg);
+                        const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg,
+                        const RunState* R = nullptr);
+// Checks eps = p/q and mu against the graph (Def 2.3, Def 2.4, the 64-bit
+// range of the test) and reduces p/q; SCAN_OK or the error code.
+int check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu);
 int collect_stats(scan_graph* g, hipStream_t s, bool timing);
 
 // Sets the thread-local message returned by scan_last_error; returns code.
