@@ -111,6 +111,14 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
 /* Releases every device and host resource of the graph.  NULL is accepted. */
 int scan_graph_destroy(scan_graph* g);
 
+/* Upper bound of the device bytes scan_graph_create allocates for an in-memory
+ * graph of n vertices and nnz arcs under opts (NULL = defaults): row offsets,
+ * neighbour ids (and their degree-ranked copy when opts->hub_ranked is set and
+ * n > 2^19), the oriented edge list, its worklist and edge states, per-vertex
+ * state and output staging, plus 1 MiB for small tables.  A graph created with
+ * device_budget_bytes below this value takes the partition-based path. */
+int scan_graph_footprint(int32_t n, int64_t nnz, const scan_opts* opts, uint64_t* bytes);
+
 /* Sizes of a created graph: vertices, arcs, undirected edges, maximum degree. */
 int scan_graph_info(const scan_graph* g, int32_t* n, int64_t* nnz, int64_t* m, int32_t* max_degree);
 
@@ -212,9 +220,16 @@ int scan_last_stats(const scan_graph* g, scan_stats* out);
  * the same result as scan_run, without recomputing any intersection.
  * Requests are admitted onto `num_slots` slots (one HIP stream and scratch
  * each) as slots free up, so queries that arrive while others run overlap on
- * the device.  A graph whose footprint would exceed opts->device_budget_bytes
- * (0 = no cap) stays in host memory and its queries run through the budgeted
- * scan_graph_create/scan_run path.  All functions are thread-safe.
+ * the device.  Admission: a graph is made resident when the bytes already
+ * held plus its footprint (scan_graph_footprint with the server's options,
+ * plus 12 bytes per edge for the cached counts and closed-size products) plus
+ * what the slots' scratch would grow by (18 bytes per vertex and 1 per edge of
+ * the largest resident graph, per slot) fit opts->device_budget_bytes (0 = no
+ * cap).  Otherwise it stays in host memory and its queries run on a fallback
+ * thread with its own stream, through a partition-based graph built with the
+ * budget left over (kept, and counted as held, until a query of another
+ * non-resident graph or an admission needs the memory); resident queries keep
+ * being admitted and completed meanwhile.  All functions are thread-safe.
  */
 typedef struct scan_server scan_server;
 

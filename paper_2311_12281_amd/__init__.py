@@ -32,7 +32,7 @@ EXPORTED = [
     "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph", "scan_server_submit",
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
-    "scan_run_batch", "scan_run_device_noalloc",
+    "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
         L.scan_graph_create.argtypes = [i32, i64, vp, vp, P(scan_opts), P(vp)]
         L.scan_graph_destroy.argtypes = [vp]
         L.scan_graph_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
+        L.scan_graph_footprint.argtypes = [i32, i64, P(scan_opts), P(u64)]
         L.scan_run.argtypes = [vp, i64, i64, i32, vp, vp]
         L.scan_run_device.argtypes = [vp, i64, i64, i32, vp, vp, vp]
         L.scan_run_device_noalloc.argtypes = [vp, i64, i64, i32, vp, vp, vp]
@@ -142,7 +143,8 @@ def lib():
                      "scan_device_copy", "scan_h2d_rate", "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph",
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
-                     "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc"):
+                     "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc",
+                     "scan_graph_footprint"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -202,6 +204,13 @@ def scan_graph_create(n: int, nnz: int, row_ptr: np.ndarray, col_idx: np.ndarray
 
 def scan_graph_destroy(g) -> None:
     _check(lib().scan_graph_destroy(g))
+
+
+def scan_graph_footprint(n: int, nnz: int, opts: scan_opts | None = None) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().scan_graph_footprint(int(n), int(nnz), ctypes.byref(opts) if opts is not None else None,
+                                      ctypes.byref(b)))
+    return int(b.value)
 
 
 def scan_graph_info(g) -> tuple[int, int, int, int]:

@@ -174,6 +174,18 @@ int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
   return SCAN_OK;
 }
 
+uint64_t scan::graph_device_bytes(const scan_graph* g) {
+  if (g->partitioned) return 0;
+  const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, m = (uint64_t)g->m;
+  const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
+  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6;
+  if (g->d_hci) b += 4 * (nnz + kColPad);
+  b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
+  if (g->d_out_labels) b += 5 * n;
+  if (g->d_counts) b += 4 * nnz;
+  return b;
+}
+
 int scan::check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu) {
   if (p < 1 || q < p) return fail(SCAN_E_INVAL, "eps must satisfy 1 <= eps_num <= eps_den (got %lld/%lld)",
                                   (long long)p, (long long)q);
@@ -376,6 +388,15 @@ int scan_graph_destroy(scan_graph* g) {
     release(g);
   }
   delete g;
+  return SCAN_OK;
+}
+
+int scan_graph_footprint(int32_t n, int64_t nnz, const scan_opts* opts, uint64_t* bytes) {
+  if (n < 0 || nnz < 0 || !bytes) return fail(SCAN_E_INVAL, "n, nnz must be >= 0 and bytes non-NULL");
+  scan_opts o;
+  if (opts) o = *opts;
+  else scan_opts_default(&o);
+  *bytes = inmemory_footprint(n, nnz, o.hub_ranked != 0);
   return SCAN_OK;
 }
 

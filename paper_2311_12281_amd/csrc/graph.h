@@ -134,8 +134,11 @@ int fail_hip(hipError_t e, const char* what);
 // may be null.
 int run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hipStream_t s);
 
-// Partitioned path (partition.hip).  device bytes the in-memory layout needs:
+// Partitioned path (partition.hip).  device bytes the in-memory layout needs
+// (an upper bound of what scan_graph_create allocates):
 uint64_t inmemory_footprint(int32_t n, int64_t nnz, bool ranked);
+// Device bytes an in-memory graph holds now (its buffers as allocated).
+uint64_t graph_device_bytes(const scan_graph* g);
 // Plans blocks and chunks for `budget` device bytes, copies the CSR to pinned
 // memory and allocates the resident state and streaming buffers.
 int part_validate(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, bool full);

@@ -1257,16 +1257,27 @@ __global__ void k_rt_init(int32_t n, int32_t* lower, int32_t* parent) {
   parent[u] = (int32_t)u;
 }
 
-__global__ void k_rt_edges(int64_t m, const int2* edges, const int64_t* rp, const int32_t* ecount,
-                           uint64_t p, uint64_t q, uint8_t* state, int32_t* lower) {
+// |N[u]| |N[v]| of every oriented edge, computed once when a graph is added,
+// so that a query streams it with the count instead of gathering row offsets.
+__global__ void k_closed_products(int64_t m, const int2* edges, const int64_t* rp, uint64_t* ab) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; e < m; e += stride) {
     const int2 uv = edges[e];
     const uint64_t a = (uint64_t)(rp[uv.x + 1] - rp[uv.x]) + 1;
     const uint64_t b = (uint64_t)(rp[uv.y + 1] - rp[uv.y]) + 1;
+    ab[e] = a * b;
+  }
+}
+
+__global__ void k_rt_edges(int64_t m, const int2* edges, const int32_t* ecount, const uint64_t* ab,
+                           uint64_t p, uint64_t q, uint8_t* state, int32_t* lower) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < m; e += stride) {
+    const int2 uv = edges[e];
     const uint64_t cq = (uint64_t)ecount[e] * q;
-    const bool sim = cq * cq >= (p * p) * (a * b);
+    const bool sim = cq * cq >= (p * p) * ab[e];
     state[e] = sim ? SIM_YES : SIM_NO;
     if (sim) {
       atomicAdd(lower + uv.x, 1);
@@ -1430,13 +1441,17 @@ void launch_hub_outlier_edges(hipStream_t s, int64_t m, const int2* edges, const
 }
 
 
-void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
-                        const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
+void launch_closed_products(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, uint64_t* ab) {
+  if (m > 0) k_closed_products<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, rp, ab);
+}
+
+void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int2* edges, const int32_t* ecount,
+                        const uint64_t* ab, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
                         uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
                         int32_t* out_labels, uint8_t* out_roles, int32_t split) {
   if (n <= 0) return;
   k_rt_init<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, lower, parent);
-  if (m > 0) k_rt_edges<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, rp, ecount, p, q, state, lower);
+  if (m > 0) k_rt_edges<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, ecount, ab, p, q, state, lower);
   k_rt_roles<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, mu, lower, role);
   if (m > 0) k_hook<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, edges, state, role, parent);
   k_flatten<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, parent, label);

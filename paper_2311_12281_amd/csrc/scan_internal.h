@@ -159,9 +159,11 @@ void launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 void launch_hub_outlier_edges(hipStream_t s, int64_t m, const int2* edges, const int32_t* label, int32_t* first,
                               uint8_t* role);
 
-// Serving: one query from cached per-edge closed counts (no intersections).
-void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int64_t* rp, const int2* edges,
-                        const int32_t* ecount, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
+// Serving: |N[u]| |N[v]| per oriented edge (once per graph), then one query
+// from cached per-edge closed counts and those products (no intersections).
+void launch_closed_products(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, uint64_t* ab);
+void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int2* edges, const int32_t* ecount,
+                        const uint64_t* ab, uint64_t p, uint64_t q, int32_t mu, int32_t* lower,
                         uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
                         int32_t* out_labels, uint8_t* out_roles, int32_t split);
 

@@ -8,10 +8,14 @@
 // running overlap on the device.  Completion is detected with events, results
 // are copied out of the slot's pinned buffers and the slot is reused.
 //
-// Memory admission: a graph is made resident only if its footprint (graph
-// layout plus cached counts plus, when it is the largest, the slots' scratch)
-// fits the budget; otherwise it is kept in host memory and its queries run
-// through scan_graph_create with the remaining budget and scan_run.
+// Memory admission: a graph is made resident only if its footprint (the
+// in-memory layout as scan_graph_create builds it, degree-ranked rows
+// included, plus the cached counts and closed-size products, plus what the
+// slots' scratch would grow by) fits the budget; otherwise it is kept in host
+// memory and its queries run on a fallback worker thread with its own stream,
+// through a partitioned scan_graph_create with the remaining budget (kept for
+// the next query of the same graph) and scan_run, while the dispatcher keeps
+// admitting and completing resident queries.
 #include "graph.h"
 
 #include <chrono>
@@ -33,6 +37,7 @@ struct ServedGraph {
   bool resident = false;
   scan_graph* g = nullptr;       // resident: device layout
   int32_t* d_ecount = nullptr;   // resident: closed count per oriented edge
+  uint64_t* d_ab = nullptr;      // resident: |N[u]| |N[v]| per oriented edge
   uint64_t bytes = 0;            // device bytes held while resident
   std::vector<int64_t> h_rp;     // non-resident: host copy
   std::vector<int32_t> h_ci;
@@ -66,10 +71,22 @@ struct Slot {
 
 uint64_t slot_bytes(int32_t n, int64_t m) { return 18ull * (uint64_t)n + (uint64_t)m; }
 
-uint64_t graph_bytes(int32_t n, int64_t nnz) {
+// Peak device bytes of adding a graph: the in-memory layout as
+// scan_graph_create builds it (with the degree-ranked copy of the rows where
+// the options ask for it), the cached closed counts (4 bytes per edge) and
+// closed-size products (8 bytes per edge).
+uint64_t graph_bytes(int32_t n, int64_t nnz, const scan_opts& o) {
   const uint64_t m = (uint64_t)nnz / 2;
-  // layout (row_ptr, col_idx, oriented edges, worklist) + per-run state + cached counts
-  return 8ull * ((uint64_t)n + 1) + 4ull * nnz + 8ull * m + 4ull * m + 22ull * n + 1ull * m + 4ull * m;
+  return inmemory_footprint(n, nnz, o.hub_ranked != 0) + 12ull * m;
+}
+
+void release_resident(ServedGraph* G) {
+  if (G->d_ecount) (void)hipFree(G->d_ecount);
+  if (G->d_ab) (void)hipFree(G->d_ab);
+  G->d_ecount = nullptr;
+  G->d_ab = nullptr;
+  if (G->g) scan_graph_destroy(G->g);
+  G->g = nullptr;
 }
 
 void free_slot_buffers(Slot& s) {
@@ -106,6 +123,15 @@ hipError_t alloc_slot_buffers(Slot& s, int32_t n, int64_t m) {
 
 }  // namespace
 
+// The partitioned graph the fallback worker built last, kept for the next
+// query of the same non-resident graph; its budget counts as resident bytes.
+struct FallbackGraph {
+  int32_t gid = -1;
+  scan_graph* g = nullptr;
+  uint64_t bytes = 0;
+  bool busy = false;  // a query is running on it (outside the server lock)
+};
+
 struct scan_server {
   scan_opts opts{};
   uint64_t budget = 0;  // 0 = no cap
@@ -113,10 +139,13 @@ struct scan_server {
   std::mutex mu;
   std::condition_variable cv_work;  // dispatcher wake-up
   std::condition_variable cv_done;  // waiters
+  std::condition_variable cv_fb;    // fallback worker wake-up
   std::map<int32_t, std::unique_ptr<ServedGraph>> graphs;
   int32_t next_gid = 0;
   int64_t next_req = 1;
   std::deque<std::shared_ptr<Request>> pending;
+  std::deque<std::shared_ptr<Request>> fb_pending;  // queries of non-resident graphs
+  FallbackGraph fb;
   std::map<int64_t, std::shared_ptr<Request>> requests;
   std::vector<Slot> slots;
   int32_t slot_n = 0;  // slot scratch capacity
@@ -124,29 +153,80 @@ struct scan_server {
   int64_t completed = 0;
   bool stop = false;
   bool pause_dispatch = false;  // set while slot buffers are being resized
+  bool dispatch_done = false;   // the dispatcher has stopped (no more fallback queries)
   std::thread worker;
+  std::thread fb_worker;
 };
 
 namespace {
 
-// Host path for a graph kept outside the device (over the admission limit):
-// a budgeted scan_graph_create + scan_run.  Called without the server lock;
-// the result goes to the caller's buffers and is published under the lock.
-int run_fallback(const ServedGraph* G, uint64_t budget, const scan_opts& base, int64_t p, int64_t q, int32_t mu,
-                 std::vector<int32_t>& labels, std::vector<uint8_t>& roles, std::string& error) {
-  scan_opts o = base;
-  o.hip_stream = nullptr;
-  o.device_budget_bytes = budget;
-  scan_graph* g = nullptr;
-  labels.resize((size_t)G->n);
-  roles.resize((size_t)G->n);
-  int rc = scan_graph_create(G->n, G->nnz, G->h_rp.data(), G->h_ci.data(), &o, &g);
-  if (rc == SCAN_OK) {
-    rc = scan_run(g, p, q, mu, labels.data(), roles.data());
-    scan_graph_destroy(g);
+void finish(scan_server* S, const std::shared_ptr<Request>& r) {
+  r->t_done = Clock::now();
+  S->completed++;
+  S->cv_done.notify_all();
+}
+
+// Drops the cached partitioned graph (server lock held; not busy).
+void fallback_evict(scan_server* S) {
+  if (S->fb.g) scan_graph_destroy(S->fb.g);
+  S->resident_bytes -= S->fb.bytes;
+  S->fb = FallbackGraph();
+}
+
+// Fallback worker: queries of graphs kept outside the device, one at a time,
+// each through a partitioned graph (built with the budget left over, on its
+// own library stream) that is kept for the next query of the same graph.  Runs
+// beside the dispatcher, which keeps admitting and completing resident queries.
+void fallback_loop(scan_server* S) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    S->cv_fb.wait(lk, [&] { return S->dispatch_done || !S->fb_pending.empty(); });
+    if (S->fb_pending.empty()) break;  // the dispatcher has stopped and nothing is left
+    auto r = S->fb_pending.front();
+    S->fb_pending.pop_front();
+    ServedGraph* G = S->graphs[r->gid].get();
+    int rc = SCAN_OK;
+    std::string error;
+    if (S->fb.gid != r->gid) {
+      fallback_evict(S);
+      const uint64_t budget = S->budget > S->resident_bytes ? S->budget - S->resident_bytes : 1;
+      S->resident_bytes += budget;
+      S->fb.gid = r->gid;
+      S->fb.bytes = budget;
+      S->fb.busy = true;
+      scan_opts o = S->opts;
+      o.hip_stream = nullptr;
+      o.device_budget_bytes = budget;
+      scan_graph* g = nullptr;
+      lk.unlock();
+      // the host CSR stays valid: the graph is not removed while a query on it is in flight
+      rc = scan_graph_create(G->n, G->nnz, G->h_rp.data(), G->h_ci.data(), &o, &g);
+      if (rc != SCAN_OK) error = scan_last_error();
+      lk.lock();
+      S->fb.g = g;
+      S->fb.busy = false;
+      if (rc != SCAN_OK) fallback_evict(S);
+    }
+    if (rc == SCAN_OK) {
+      scan_graph* g = S->fb.g;
+      S->fb.busy = true;
+      std::vector<int32_t> labels((size_t)G->n);
+      std::vector<uint8_t> roles((size_t)G->n);
+      const int64_t p = r->p, q = r->q;
+      const int32_t mu = r->mu;
+      lk.unlock();
+      rc = scan_run(g, p, q, mu, labels.data(), roles.data());
+      if (rc != SCAN_OK) error = scan_last_error();
+      lk.lock();
+      S->fb.busy = false;
+      r->labels.swap(labels);
+      r->roles.swap(roles);
+    }
+    r->error = error;
+    r->status = rc;
+    G->inflight--;
+    finish(S, r);
   }
-  if (rc != SCAN_OK) error = scan_last_error();
-  return rc;
 }
 
 // Starts one request on a free slot (server lock held).  Returns false if
@@ -163,7 +243,7 @@ bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& 
     r->error = "slot scratch smaller than the graph";
     return false;
   }
-  launch_rethreshold(slot.stream, G->n, G->m, g->d_rp, g->d_edges, G->d_ecount, (uint64_t)p, (uint64_t)q,
+  launch_rethreshold(slot.stream, G->n, G->m, g->d_edges, G->d_ecount, G->d_ab, (uint64_t)p, (uint64_t)q,
                      r->mu, slot.d_lower, slot.d_role, slot.d_parent, slot.d_label, slot.d_state,
                      slot.d_out_labels, slot.d_out_roles, S->opts.hub_outlier ? 1 : 0);
   hipError_t e = hipGetLastError();
@@ -180,12 +260,6 @@ bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& 
   G->inflight++;
   slot.req = r;
   return true;
-}
-
-void finish(scan_server* S, const std::shared_ptr<Request>& r) {
-  r->t_done = Clock::now();
-  S->completed++;
-  S->cv_done.notify_all();
 }
 
 void worker_loop(scan_server* S) {
@@ -212,44 +286,44 @@ void worker_loop(scan_server* S) {
       finish(S, r);
       progress = true;
     }
-    // admissions: as many queued requests as there are free slots
-    for (auto& slot : S->slots) {
-      if (S->pause_dispatch || slot.req || S->pending.empty()) continue;
-      auto r = S->pending.front();
-      S->pending.pop_front();
-      progress = true;
-      auto it = S->graphs.find(r->gid);
-      ServedGraph* G = it == S->graphs.end() ? nullptr : it->second.get();
+    // admissions: queries of non-resident graphs go to the fallback worker;
+    // resident ones, in order of arrival, onto free slots
+    for (auto it = S->pending.begin(); it != S->pending.end() && !S->pause_dispatch;) {
+      auto r = *it;
+      auto git = S->graphs.find(r->gid);
+      ServedGraph* G = git == S->graphs.end() ? nullptr : git->second.get();
       if (!G) {
         r->status = SCAN_E_INVAL;
         r->error = "unknown graph id";
         finish(S, r);
       } else if (!G->resident) {
         G->inflight++;
-        const uint64_t budget = S->budget > S->resident_bytes ? S->budget - S->resident_bytes : 1;
-        const scan_opts base = S->opts;
-        const int64_t p = r->p, q = r->q;
-        const int32_t mu = r->mu;
-        std::vector<int32_t> labels;
-        std::vector<uint8_t> roles;
-        std::string error;
-        lk.unlock();
-        const int rc = run_fallback(G, budget, base, p, q, mu, labels, roles, error);
-        lk.lock();
-        r->labels.swap(labels);
-        r->roles.swap(roles);
-        r->error = error;
-        r->status = rc;
-        G->inflight--;
-        finish(S, r);
-        break;  // slots may have changed state meanwhile
-      } else if (!launch_on_slot(S, slot, r, G)) {
-        finish(S, r);
+        S->fb_pending.push_back(r);
+        S->cv_fb.notify_one();
+      } else {
+        Slot* free_slot = nullptr;
+        for (auto& slot : S->slots)
+          if (!slot.req) {
+            free_slot = &slot;
+            break;
+          }
+        if (!free_slot) {
+          ++it;
+          continue;
+        }
+        if (!launch_on_slot(S, *free_slot, r, G)) finish(S, r);
       }
+      it = S->pending.erase(it);
+      progress = true;
     }
     bool busy = false;
     for (auto& slot : S->slots) busy = busy || (bool)slot.req;
-    if (S->stop && !busy && S->pending.empty()) break;
+    if (S->stop && !busy && S->pending.empty()) {
+      // every request is on its way: the fallback worker may finish its queue and stop
+      S->dispatch_done = true;
+      S->cv_fb.notify_all();
+      break;
+    }
     if (!progress) {
       if (busy) {
         // poll the running slots without holding the lock
@@ -301,6 +375,7 @@ int scan_server_create(const scan_opts* opts, int32_t num_slots, scan_server** o
     }
   }
   S->worker = std::thread(worker_loop, S);
+  S->fb_worker = std::thread(fallback_loop, S);
   *out = S;
   return SCAN_OK;
 }
@@ -313,41 +388,67 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
   G->n = n;
   G->nnz = nnz;
   G->m = nnz / 2;
-  const uint64_t gbytes = graph_bytes(n, nnz);
+  const uint64_t gbytes = graph_bytes(n, nnz, S->opts);
   bool resident;
   {
-    // admission: reserve the graph's bytes and what the slots would grow by
+    // admission: reserve the graph's peak bytes and what the slots would grow
+    // by; an idle cached fallback graph gives its budget back first if needed
     std::lock_guard<std::mutex> lk(S->mu);
     const int32_t new_n = n > S->slot_n ? n : S->slot_n;
     const int64_t new_m = G->m > S->slot_m ? G->m : S->slot_m;
     const uint64_t grow = S->slots.size() * (slot_bytes(new_n, new_m) - slot_bytes(S->slot_n, S->slot_m));
-    resident = S->budget == 0 || S->resident_bytes + gbytes + grow <= S->budget;
+    auto fits = [&] { return S->budget == 0 || S->resident_bytes + gbytes + grow <= S->budget; };
+    resident = fits();
+    if (!resident && S->fb.g && !S->fb.busy) {
+      fallback_evict(S);
+      resident = fits();
+    }
     if (resident) S->resident_bytes += gbytes;
   }
+  uint64_t held = gbytes;  // bytes reserved for this graph so far
   if (resident) {
     scan_opts o = S->opts;
     o.device_budget_bytes = 0;
     scan_graph* g = nullptr;
     int rc = scan_graph_create(n, nnz, row_ptr, col_idx, &o, &g);
+    G->g = g;
     if (rc == SCAN_OK && g->m > 0) {
       hipError_t e = hipMalloc((void**)&G->d_ecount, sizeof(int32_t) * (size_t)g->m);
+      if (e == hipSuccess) e = hipMalloc((void**)&G->d_ab, sizeof(uint64_t) * (size_t)g->m);
       if (e != hipSuccess) {
         rc = fail_hip(e, "hipMalloc counts");
       } else {
         std::lock_guard<std::mutex> glk(g->lock);
         rc = run_counts(g, nullptr, G->d_ecount, g->stream);
+        if (rc == SCAN_OK) {
+          launch_closed_products(g->stream, g->m, g->d_rp, g->d_edges, G->d_ab);
+          e = hipGetLastError();
+          if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+          if (e != hipSuccess) rc = fail_hip(e, "closed-size products");
+        }
       }
     }
-    if (rc != SCAN_OK) {
-      if (G->d_ecount) (void)hipFree(G->d_ecount);
-      if (g) scan_graph_destroy(g);
+    if (rc == SCAN_OK) {
+      // queries never intersect again: the rows renamed by degree rank, used
+      // only by the counting run, are released
+      if (g->d_hci) {
+        (void)hipFree(g->d_hci);
+        g->d_hci = nullptr;
+      }
+      const uint64_t now = graph_device_bytes(g) + 12ull * (uint64_t)g->m;
       std::lock_guard<std::mutex> lk(S->mu);
-      S->resident_bytes -= gbytes;
+      S->resident_bytes -= held;
+      S->resident_bytes += now;
+      held = now;
+    }
+    if (rc != SCAN_OK) {
+      release_resident(G.get());
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->resident_bytes -= held;
       return rc;
     }
-    G->g = g;
     G->resident = true;
-    G->bytes = gbytes;
+    G->bytes = held;
   } else {
     G->h_rp.assign(row_ptr, row_ptr + n + 1);
     if (nnz > 0) G->h_ci.assign(col_idx, col_idx + nnz);
@@ -364,10 +465,9 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
       for (auto& s : S->slots) (void)alloc_slot_buffers(s, S->slot_n, S->slot_m);
       S->pause_dispatch = false;
       S->cv_work.notify_one();
-      S->resident_bytes -= gbytes;
+      S->resident_bytes -= held;
       lk.unlock();
-      if (G->d_ecount) (void)hipFree(G->d_ecount);
-      scan_graph_destroy(G->g);
+      release_resident(G.get());
       return fail_hip(e, "slot scratch");
     }
     S->resident_bytes += S->slots.size() * (slot_bytes(new_n, new_m) - slot_bytes(S->slot_n, S->slot_m));
@@ -395,9 +495,9 @@ int scan_server_remove_graph(scan_server* S, int32_t gid) {
       if (r->gid == gid) return false;
     return true;
   });
+  if (S->fb.gid == gid) fallback_evict(S);  // idle: its queries are done
   if (G->resident) {
-    if (G->d_ecount) (void)hipFree(G->d_ecount);
-    scan_graph_destroy(G->g);
+    release_resident(G);
     S->resident_bytes -= G->bytes;
   }
   S->graphs.erase(it);
@@ -470,12 +570,11 @@ int scan_server_destroy(scan_server* S) {
     S->cv_work.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
+  if (S->fb_worker.joinable()) S->fb_worker.join();
+  fallback_evict(S);
   for (auto& kv : S->graphs) {
     ServedGraph* G = kv.second.get();
-    if (G->resident) {
-      if (G->d_ecount) (void)hipFree(G->d_ecount);
-      scan_graph_destroy(G->g);
-    }
+    if (G->resident) release_resident(G);
   }
   for (auto& s : S->slots) {
     free_slot_buffers(s);

@@ -101,3 +101,72 @@ def test_serving_admission_falls_back_to_partitioned_path():
                 l, r, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
                 ol, orr = oracle.scan(g, p, q, mu, threads=oracle.max_threads())
                 assert_same(l, r, ol, orr, f"admission gid={gid} eps={p}/{q} mu={mu}")
+
+
+def _served_bytes(g, **opts):
+    """Peak device bytes the server reserves for adding g (its admission rule)."""
+    return S.scan_graph_footprint(g.n, g.nnz, S.make_opts(**opts)) + 12 * g.m
+
+
+def test_serving_admission_counts_the_ranked_rows():
+    """A graph of more than 2^19 vertices gets a degree-ranked copy of its rows
+    when it is created; admission must count it.  A budget that holds the graph
+    without that copy (but not with it) keeps the graph on the host."""
+    g = gg.rmat(20, 4, seed=23)
+    assert g.n > (1 << 19)
+    slots = 18 * g.n + g.m  # one slot
+    without = _served_bytes(g, hub_ranked=False) + slots
+    with_ranked = _served_bytes(g) + slots
+    assert with_ranked - without >= 4 * g.nnz
+    oc = oracle.counts(g, threads=oracle.max_threads())
+    for budget, resident in ((without + (1 << 20), 0), (with_ranked + (1 << 20), 1)):
+        note("serving ranked-row admission", budget, resident)
+        with S.Server(num_slots=1, budget=budget) as srv:
+            gid = srv.add(g)
+            assert srv.info()["resident_graphs"] == resident
+            assert srv.info()["resident_bytes"] <= budget
+            for p, q, mu in [(1, 5, 3), (1, 2, 2)]:
+                l, r, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
+                ol, orr = oracle.cluster(g, oc, p, q, mu)
+                assert_same(l, r, ol, orr, f"ranked admission resident={resident} eps={p}/{q} mu={mu}")
+
+
+def test_serving_resident_queries_complete_while_fallback_runs():
+    """A query on a graph kept on the host runs on the fallback worker; queries
+    on resident graphs submitted after it are admitted and completed while it
+    runs (no head-of-line blocking), and every answer equals the oracle's."""
+    import time
+
+    smalls = [gg.rmat(11, 8, seed=31 + k) for k in range(3)]
+    big = gg.rmat(18, 16, seed=34)
+    nslots = 4
+    resident_need = sum(_served_bytes(g) for g in smalls) + nslots * max(18 * g.n + g.m for g in smalls)
+    budget = resident_need + (24 << 20)
+    assert _served_bytes(big) > budget - resident_need  # the big graph cannot be resident
+    with S.Server(num_slots=nslots, budget=budget) as srv:
+        gids = [srv.add(g) for g in smalls]
+        b = srv.add(big)
+        info = srv.info()
+        assert info["resident_graphs"] == len(smalls) and info["graphs"] == len(smalls) + 1
+        note("fallback query + resident queries")
+        t_fb = time.perf_counter()
+        rf = srv.submit(b, 1, 5, 4)
+        sub = []
+        for k in range(30):
+            gi = k % len(smalls)
+            sub.append((time.perf_counter(), srv.submit(gids[gi], 1 + k % 9, 10, 2 + k % 7), gi, 1 + k % 9, 2 + k % 7))
+        done_res = []
+        for t0, r, gi, p, mu in sub:
+            l, ro, lat = srv.wait(r, gids[gi])
+            done_res.append(t0 + lat * 1e-3)
+            ol, orr = oracle.scan(smalls[gi], p, 10, mu)
+            assert_same(l, ro, ol, orr, f"resident graph {gi} eps={p}/10 mu={mu}")
+        l, ro, lat = srv.wait(rf, b)
+        done_fb = t_fb + lat * 1e-3
+        ol, orr = oracle.scan(big, 1, 5, 4, threads=oracle.max_threads())
+        assert_same(l, ro, ol, orr, "fallback graph")
+        assert max(done_res) < done_fb, (max(done_res) - t_fb, done_fb - t_fb)
+        # the partitioned graph is kept: a second query of it needs no new build
+        l2, ro2, lat2 = srv.wait(srv.submit(b, 1, 5, 4), b)
+        assert np.array_equal(l2, l) and np.array_equal(ro2, ro)
+        assert srv.info()["resident_bytes"] <= budget
