@@ -160,6 +160,8 @@ def chung_lu_weights(n: int, mean_deg: float = 30.0, exponent: float = 2.1,
     lo, hi = 0.0, float(mean_deg) * n
     for _ in range(200):
         s = 0.5 * (lo + hi)
+        if s <= lo or s >= hi:
+            break  # the interval cannot shrink any further: later rounds change nothing
         mean = np.minimum(s * base, max_deg).mean()
         if mean < mean_deg:
             lo = s
@@ -183,13 +185,24 @@ def chung_lu(n: int, mean_deg: float = 30.0, exponent: float = 2.1,
 def permute(g: CSR, seed: int) -> tuple[CSR, np.ndarray]:
     """Relabel vertices by a seeded random permutation; returns (graph, perm)
     with perm[old] = new."""
-    lib = _load()
     perm = np.random.default_rng(seed).permutation(g.n).astype(np.int32)
+    return relabel(g, perm), perm
+
+
+def reverse_ids(g: CSR) -> CSR:
+    """The same graph with vertex v renamed n - 1 - v."""
+    return relabel(g, np.arange(g.n - 1, -1, -1, dtype=np.int32))
+
+
+def relabel(g: CSR, perm: np.ndarray) -> CSR:
+    """The same graph with vertex v renamed perm[v] (perm a permutation)."""
+    lib = _load()
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
     rp = np.empty_like(g.row_ptr)
     ci = np.empty(max(1, g.nnz), dtype=np.int32)
     lib.gg_permute(g.n, _ptr(g.row_ptr), _ptr(np.ascontiguousarray(g.col_idx)), _ptr(perm),
                    _ptr(rp), _ptr(ci))
-    return CSR(g.n, rp, ci[: g.nnz]), perm
+    return CSR(g.n, rp, ci[: g.nnz])
 
 
 # ---------------------------------------------------------------------------
@@ -233,3 +246,38 @@ def planted_batch(count: int, seed: int = 4, n_lo: int = 100, n_hi: int = 20000)
 
 def num_threads() -> int:
     return int(_load().gg_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: resident R-MAT graphs of mixed size plus later uploads,
+# and a stream of (graph, eps = k/10, mu) queries.
+
+@dataclass
+class RmatSpec:
+    scale: int
+    edge_factor: int
+    seed: int
+
+    def make(self) -> CSR:
+        return rmat(self.scale, self.edge_factor, seed=self.seed)
+
+
+def serving_specs(count: int = 64, uploads: int = 8, seed: int = 5, scale_lo: int = 16,
+                  scale_hi: int = 23, ef_lo: int = 8, ef_hi: int = 32):
+    """R-MAT graphs (same a, b, c, d as the single-graph workload) with scale
+    ~ U{scale_lo..scale_hi} and edge factor ~ U{ef_lo..ef_hi}: `count` resident
+    from the start, then `uploads` added while queries run.  Graph k uses
+    generator seed 100 + k."""
+    rng = np.random.default_rng(seed)
+    specs = [RmatSpec(int(rng.integers(scale_lo, scale_hi + 1)), int(rng.integers(ef_lo, ef_hi + 1)), 100 + k)
+             for k in range(count + uploads)]
+    return specs[:count], specs[count:]
+
+
+def serving_queries(num: int, num_graphs: int, seed: int = 6):
+    """Queries (graph index, p, q, mu) with graph uniform, eps = k/10 for
+    k ~ U{1..9}, mu ~ U{2..20}."""
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(num_graphs)), int(rng.integers(1, 10)), 10, int(rng.integers(2, 21)))
+            for _ in range(num)]
+

@@ -229,20 +229,28 @@ int64_t gg_symmetrize(int32_t n, int64_t npairs, const int32_t* src, const int32
                       int64_t* raw_rp, int32_t* raw_ci, int64_t* deg) {
   if (n < 0 || npairs < 0) return -1;
   std::memset(raw_rp, 0, sizeof(int64_t) * ((size_t)n + 1));
+  int bad = 0;
+  // counts and scatter in parallel with atomic cursors: the order inside a
+  // raw row depends on the threads, but every row is sorted and deduplicated
+  // below, so the result does not
+#pragma omp parallel for schedule(static) reduction(| : bad)
   for (int64_t i = 0; i < npairs; ++i) {
-    int32_t u = src[i], v = dst[i];
-    if (u < 0 || v < 0 || u >= n || v >= n) return -2;
+    const int32_t u = src[i], v = dst[i];
+    if (u < 0 || v < 0 || u >= n || v >= n) { bad = 1; continue; }
     if (u == v) continue;
-    raw_rp[u + 1]++;
-    raw_rp[v + 1]++;
+    __atomic_fetch_add(raw_rp + u + 1, 1, __ATOMIC_RELAXED);
+    __atomic_fetch_add(raw_rp + v + 1, 1, __ATOMIC_RELAXED);
   }
+  if (bad) return -2;
   for (int32_t u = 0; u < n; ++u) raw_rp[u + 1] += raw_rp[u];
   std::vector<int64_t> cur(raw_rp, raw_rp + n);
+  int64_t* cp = cur.data();
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < npairs; ++i) {
-    int32_t u = src[i], v = dst[i];
+    const int32_t u = src[i], v = dst[i];
     if (u == v) continue;
-    raw_ci[cur[u]++] = v;
-    raw_ci[cur[v]++] = u;
+    raw_ci[__atomic_fetch_add(cp + u, 1, __ATOMIC_RELAXED)] = v;
+    raw_ci[__atomic_fetch_add(cp + v, 1, __ATOMIC_RELAXED)] = u;
   }
   int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 1024) reduction(+ : total)
