@@ -515,7 +515,7 @@ def bench_batched(args):
     t = time.perf_counter()
     B = S.Batch(graphs, eps, mus, autotune=True)
     create_s = time.perf_counter() - t
-    lanes, hub = B.config()
+    lanes, tile = B.config()
     B.run()
     t = time.perf_counter()
     for _ in range(args.steps):
@@ -540,7 +540,7 @@ def bench_batched(args):
     _line("edges/s (|E|/solve) exact-match, batched", m / batch_s, "edges/s",
           {"workload": f"planted_batch_{len(graphs)}", "graphs": len(graphs), "m": m},
           ms_per_batch=batch_s * 1e3, plain_edges_per_s=m / plain_s, plain_ms=plain_s * 1e3,
-          identical_to_plain=same, oracle_sample_exact=oracle_ok, autotuned_lanes=lanes, hub=hub,
+          identical_to_plain=same, oracle_sample_exact=oracle_ok, autotuned_lanes=lanes, tile_edges=tile,
           create_s=create_s)
 
 

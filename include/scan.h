@@ -262,14 +262,21 @@ int scan_server_destroy(scan_server* s);
 
 /*
  * Batched clustering: many independent graphs, each with its own eps and mu,
- * clustered together.  The graphs are packed into one disjoint union on the
- * device (every vertex knows its graph and looks up that graph's parameters),
- * and the whole pipeline for the batch is captured once into a HIP graph, so
- * one run is a single graph launch whatever the number of graphs.  With
- * autotune = 1 the library times candidate kernels per degree bucket (lane
- * group width; LDS-hash or group kernel for the last bucket) on this batch and
- * keeps the fastest; SCAN_AUTOTUNE_CACHE names an optional file that caches
- * the choice by batch shape.
+ * clustered together (the method of Algorithms 1-3 applied to every graph).
+ * The graphs are packed into one disjoint union on the device (every vertex
+ * knows its graph and looks up that graph's parameters), and one persistent
+ * kernel clusters the whole batch: its blocks take (graph, phase, tile) work
+ * items from a device queue, every graph moves through the phases on its own
+ * (a per-graph count of the unfinished tiles of its current phase; the block
+ * finishing the last one queues the next phase), and the queue reset plus
+ * that kernel are captured once into a HIP graph, so one run is a single
+ * graph launch whatever the number of graphs.  Per-graph eps and mu are read
+ * from device memory on every run.  With autotune = 1 the library times whole
+ * runs on this batch to choose, per degree bucket, the lane-group width of
+ * the intersection (4 to 64 lanes per edge, or a wave with an LDS hash set for
+ * the two buckets whose smaller side has more than 32 neighbours), and the
+ * edges per tile; SCAN_AUTOTUNE_CACHE names an optional file that caches the
+ * choice by batch shape.
  */
 typedef struct scan_batch {
   int32_t num_graphs;       /* G >= 0 */
@@ -281,26 +288,35 @@ typedef struct scan_batch {
   const int64_t* eps_num;   /* [G] */
   const int64_t* eps_den;   /* [G] */
   const int32_t* mu;        /* [G] */
-  int32_t autotune;         /* 1: choose the per-bucket kernels by timing them on this batch */
+  int32_t autotune;         /* 1: choose lane widths and tile size by timing runs of this batch */
 } scan_batch;
 
 typedef struct scan_batch_graph scan_batch_graph;
 
 /* Packs and validates the batch (each graph as in scan_graph_create), builds
- * the device layout, optionally autotunes, and captures the run. */
+ * the device layout and work-item tables, optionally autotunes, and captures
+ * the run.  Errors: SCAN_E_INVAL, SCAN_E_GRAPH, SCAN_E_RANGE (a graph's eps
+ * denominator with its maximum degree), SCAN_E_NOMEM, SCAN_E_DEVICE. */
 int scan_batch_create(const scan_batch* b, const scan_opts* opts, scan_batch_graph** out);
+
+/* Replaces every graph's eps and mu ([G] arrays, same rules as in
+ * scan_batch); the next run uses them, no new capture needed. */
+int scan_batch_set_params(scan_batch_graph* bg, const int64_t* eps_num, const int64_t* eps_den,
+                          const int32_t* mu);
 
 /* Clusters every graph of the batch: labels[vtx_off[G]] receive graph-local
  * labels (minimum core id within the graph, -1 if unclassified) and roles the
  * roles, both host, caller-owned, packed like the vertices.  replay = 1 runs
- * the captured HIP graph, 0 issues the same kernels one by one. */
+ * the captured HIP graph, 0 launches the same two kernels directly.  A run in
+ * which a block waits more than 20 s for a work item is abandoned and
+ * reported as SCAN_E_DEVICE. */
 int scan_batch_run(scan_batch_graph* bg, int32_t replay, int32_t* labels, uint8_t* roles);
 
-/* Chosen kernel per bucket: lanes[SCAN_NUM_BUCKETS] lane-group widths, *hub =
- * 1 if the last bucket uses the LDS-hash kernel. */
-int scan_batch_config(const scan_batch_graph* bg, int32_t* lanes, int32_t* hub);
+/* Chosen configuration: lanes[SCAN_NUM_BUCKETS] lane-group widths per degree
+ * bucket, *tile_edges edges per work item of the edge phases (either may be NULL). */
+int scan_batch_config(const scan_batch_graph* bg, int32_t* lanes, int32_t* tile_edges);
 
-/* Statistics of the last scan_batch_run. */
+/* Statistics of the last scan_batch_run (ms_total = device time of the run). */
 int scan_batch_stats(const scan_batch_graph* bg, scan_stats* out);
 
 int scan_batch_destroy(scan_batch_graph* bg);

@@ -32,7 +32,7 @@ EXPORTED = [
     "scan_server_create", "scan_server_add_graph", "scan_server_remove_graph", "scan_server_submit",
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
-    "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint",
+    "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint", "scan_batch_set_params",
 ]
 
 
@@ -131,6 +131,7 @@ def lib():
         L.scan_server_destroy.argtypes = [vp]
         L.scan_batch_create.argtypes = [P(scan_batch), P(scan_opts), P(vp)]
         L.scan_batch_run.argtypes = [vp, i32, vp, vp]
+        L.scan_batch_set_params.argtypes = [vp, vp, vp, vp]
         L.scan_batch_config.argtypes = [vp, vp, P(i32)]
         L.scan_batch_stats.argtypes = [vp, P(scan_stats)]
         L.scan_batch_destroy.argtypes = [vp]
@@ -144,7 +145,7 @@ def lib():
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
                      "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc",
-                     "scan_graph_footprint"):
+                     "scan_graph_footprint", "scan_batch_set_params"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -499,15 +500,23 @@ class Batch:
         return [arr[self.vtx_off[k]:self.vtx_off[k + 1]] for k in range(len(self.vtx_off) - 1)]
 
     def config(self):
+        """(lane-group width per degree bucket, edges per tile)."""
         lanes = np.zeros(NUM_BUCKETS, np.int32)
-        hub = ctypes.c_int32()
-        _check(lib().scan_batch_config(self.handle, _vp(lanes), ctypes.byref(hub)))
-        return lanes.tolist(), bool(hub.value)
+        tile = ctypes.c_int32()
+        _check(lib().scan_batch_config(self.handle, _vp(lanes), ctypes.byref(tile)))
+        return lanes.tolist(), int(tile.value)
+
+    def set_params(self, eps, mus):
+        eps_num = np.array([e[0] for e in eps], np.int64)
+        eps_den = np.array([e[1] for e in eps], np.int64)
+        mu = np.array(mus, np.int32)
+        _check(lib().scan_batch_set_params(self.handle, _vp(eps_num), _vp(eps_den), _vp(mu)))
 
     def stats(self):
         s = scan_stats()
         _check(lib().scan_batch_stats(self.handle, ctypes.byref(s)))
-        return {"ms_total": s.ms_total, "evaluated_cores": s.evaluated[1], "edges": s.edges}
+        return {"ms_total": s.ms_total, "evaluated_cores": s.evaluated[1], "edges": s.edges,
+                "evaluated": dict(zip(PHASES, list(s.evaluated))), "probes": dict(zip(PHASES, list(s.probes)))}
 
     def close(self):
         if self.handle is not None:

@@ -428,35 +428,38 @@ __device__ __forceinline__ int wave_intersect(const int32_t* Arow, int64_t du, c
   return 1;
 }
 
+// Edge counters of one pass, summed per lane and flushed once.
+struct PassCounts {
+  unsigned long long eval = 0, bound = 0, probe = 0;
+};
+
 // Every lane classifies one edge of a chunk of 64 and applies the edges that
 // need no intersection; the edges that do are then taken 64/G at a time, one
 // per group of G lanes (the edge's fields are broadcast from the lane that
 // classified it).  Buckets 0-4 use G >= d_s (one tile); G = 64 also serves the
 // last bucket when it runs without the LDS-hash kernel.
 // STAGE (buckets 4 and 5, G = 64): for an edge whose larger side has at most
-// kHubMinDegree neighbours, the wave loads nbr(v) into its own LDS hash set,
-// and every element of the smaller list is one hash probe; edges with a
-// larger side above that search nbr(v) in global memory.
-template <int MODE, int G, bool STAGE = false>
-__global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
+// kHubMinDegree neighbours, the wave loads nbr(v) into its own LDS hash set
+// (T, kWaveSlots int32), and every element of the smaller list is one hash
+// probe; edges with a larger side above that search nbr(v) in global memory.
+// Wave `wave` of `nwaves` takes the chunks wave, wave + nwaves, ... of
+// [begin, end).
+template <int MODE, int G, bool STAGE>
+__device__ __forceinline__ void group_edges(const EdgeArgs& A, int64_t begin, int64_t end, int64_t wave,
+                                            int64_t nwaves, int32_t* T, PassCounts& pc) {
   static_assert(!STAGE || G == 64, "staging is per wave");
-  if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
-  __shared__ __align__(16) int32_t stage[STAGE ? (kBlock / 64) * kWaveSlots : 1];
   constexpr int kGroups = 64 / G;
   const int lane = threadIdx.x & 63;
   const int grp = lane / G, sub = lane & (G - 1), gbase = lane & ~(G - 1);
   const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
-  unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
   int32_t staged_v = -1;  // STAGE: the vertex whose list the wave's LDS slot holds
-  for (int64_t base = A.e_begin + wave * 64; base < A.e_end; base += nwaves * 64) {
+  for (int64_t base = begin + wave * 64; base < end; base += nwaves * 64) {
     const int64_t e = base + lane;
     EdgeView ev;
     unsigned long long nb = 0;
-    classify<MODE>(A, e, e < A.e_end, ev, nb);
-    n_bound += nb;
+    classify<MODE>(A, e, e < end, ev, nb);
+    pc.bound += nb;
     bool surv = false;
     if (ev.work == 2) {
       apply<MODE>(A, e, ev, true, 0);
@@ -464,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
       if (MODE != MODE_ATTACH) apply<MODE>(A, e, ev, false, 0);
     } else if (ev.work == 1) {
       if (!exact && ev.need - 2 <= 0) {
-        ++n_eval;
+        ++pc.eval;
         apply<MODE>(A, e, ev, true, 0);
       } else {
         surv = true;
@@ -496,7 +499,6 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
         int64_t consumed;
         int verdict;
         if (STAGE && w.dv <= kHubMinDegree) {  // uniform over the wave (G = 64)
-          int32_t* T = stage + (threadIdx.x >> 6) * kWaveSlots;
           // edges are grouped by the larger side, so consecutive edges of a
           // wave mostly share it and its set is built once
           if (w.v != staged_v) {
@@ -524,8 +526,8 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
                                        gmask, cnt, consumed);
         }
         if (sub == 0) {
-          ++n_eval;
-          n_probe += (unsigned long long)consumed;
+          ++pc.eval;
+          pc.probe += (unsigned long long)consumed;
           const bool sim = verdict == 2 ? true : verdict == 3 ? false : (cnt + 2 >= w.need);
           apply<MODE>(A, we, w, MODE == MODE_COUNTS ? false : sim, cnt + 2);
         }
@@ -533,7 +535,19 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
       for (int j = 0; j < kGroups && pending; ++j) pending &= pending - 1;
     }
   }
-  flush_stats(A, MODE, n_eval, n_bound, n_probe);
+}
+
+// One bucket's pass over [A.e_begin, A.e_end), grid-stride over 64-edge chunks.
+template <int MODE, int G, bool STAGE = false>
+__global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
+  if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
+  __shared__ __align__(16) int32_t stage[STAGE ? (kBlock / 64) * kWaveSlots : 1];
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  PassCounts pc;
+  group_edges<MODE, G, STAGE>(A, A.e_begin, A.e_end, wave, nwaves, stage + (STAGE ? (threadIdx.x >> 6) * kWaveSlots : 0),
+                              pc);
+  flush_stats(A, MODE, pc.eval, pc.bound, pc.probe);
 }
 
 // Last bucket (d_u > 64), grouped by the larger side v.  A job is up to
@@ -1305,6 +1319,290 @@ __global__ void k_rt_attach(int64_t m, const int2* edges, const uint8_t* state, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched clustering in one persistent launch.  Blocks take (graph, phase,
+// tile) items: item slot k < init_items is the BP_INIT tile that init_prefix
+// assigns to it; later slots are read from the queue, where the block that
+// finished the last tile of a graph's phase wrote that graph's next phase.
+// remaining[g] counts the unfinished tiles of graph g's current phase.
+//
+// Visibility between blocks (each XCD has its own L2): a finished tile's
+// writes are released (agent-scope fence in every wave) before its count is
+// taken off remaining[g]; the block taking the last count acquires them, and
+// releases again before it writes the next phase's items; a block acquires
+// after reading an item.  A block waits for an item only while it holds a
+// claimed slot, every slot below the final fill level is eventually written by
+// a block that is running, and a slot at or above it is recognised (skipped
+// phases are counted in ctl[3]); a wall-clock watchdog nevertheless ends the
+// wait with the error flag ctl[2] set, which makes every block return.
+constexpr unsigned long long kBatchEmpty = ~0ull;
+
+__device__ __forceinline__ unsigned long long batch_item(int32_t g, int ph, int64_t t) {
+  return ((unsigned long long)(uint32_t)g << 32) | ((unsigned long long)ph << 28) | (unsigned long long)t;
+}
+
+// Edges of graph g in bucket k (ek[k]) and their first edge (lo[k]).
+__device__ __forceinline__ void batch_graph_edges(const BatchArgs& B, int32_t g, int64_t* lo, int64_t* ek) {
+#pragma unroll
+  for (int k = 0; k < kNumBuckets; ++k) {
+    const int64_t* row = B.eoff + (int64_t)k * (B.G + 1);
+    lo[k] = row[g];
+    ek[k] = row[g + 1] - row[g];
+  }
+}
+
+__device__ __forceinline__ int64_t batch_tiles(const BatchArgs& B, int32_t g, int ph) {
+  int64_t lo[kNumBuckets], ek[kNumBuckets];
+  batch_graph_edges(B, g, lo, ek);
+  return batch_phase_tiles(ph, B.vtx_off[g + 1] - B.vtx_off[g], ek, B.tile_edges, B.tile_vertices, B.split);
+}
+
+// Thread 0: claims the next slot and returns its item, or kBatchEmpty when
+// the run is over (or was abandoned).
+__device__ unsigned long long batch_take(const BatchArgs& B) {
+  const unsigned long long slot = atomicAdd(B.ctl + 0, 1ull);
+  if ((int64_t)slot >= B.total) return kBatchEmpty;
+  if ((int64_t)slot < B.init_items) {
+    int32_t lo = 0, hi = B.G;  // graph g: init_prefix[g] <= slot < init_prefix[g + 1]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (B.init_prefix[mid] <= (int64_t)slot) lo = mid;
+      else hi = mid;
+    }
+    return batch_item(lo, BP_INIT, (int64_t)slot - B.init_prefix[lo]);
+  }
+  const int64_t idx = (int64_t)slot - B.init_items;
+  const uint64_t t0 = wall_clock64();
+  while (true) {
+    const unsigned long long v = __hip_atomic_load(B.queue + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v != kBatchEmpty) return v;
+    // phases skipped so far lower the fill level; a slot at or above it is never written
+    const unsigned long long skipped = __hip_atomic_load(B.ctl + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int64_t)slot >= B.total - (int64_t)skipped) return kBatchEmpty;
+    if (__hip_atomic_load(B.ctl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return kBatchEmpty;
+    if (wall_clock64() - t0 > B.watchdog_ticks) {
+      atomicOr(B.ctl + 2, 1ull);
+      return kBatchEmpty;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void batch_group(const BatchArgs& B, int k, int64_t lo, int64_t hi, int32_t* T,
+                                            PassCounts& pc) {
+  const int64_t wave = threadIdx.x >> 6;
+  constexpr int64_t nw = kBlock / 64;
+  switch (B.lanes[k]) {
+    case 4: group_edges<MODE, 4, false>(B.A, lo, hi, wave, nw, T, pc); break;
+    case 8: group_edges<MODE, 8, false>(B.A, lo, hi, wave, nw, T, pc); break;
+    case 16: group_edges<MODE, 16, false>(B.A, lo, hi, wave, nw, T, pc); break;
+    case 32: group_edges<MODE, 32, false>(B.A, lo, hi, wave, nw, T, pc); break;
+    default:
+      if (k == 4 || k == 5) group_edges<MODE, 64, true>(B.A, lo, hi, wave, nw, T, pc);
+      else group_edges<MODE, 64, false>(B.A, lo, hi, wave, nw, T, pc);
+      break;
+  }
+}
+
+// Adds a wave's pass counters to the block's statistics.
+__device__ __forceinline__ void batch_count(unsigned long long* sh, int mode, int k, PassCounts pc) {
+  const unsigned long long ev = wave_sum(pc.eval), bd = wave_sum(pc.bound), pr = wave_sum(pc.probe);
+  if ((threadIdx.x & 63) == 0) {
+    if (ev) atomicAdd(sh + ST_EVAL + mode, ev);
+    if (bd) atomicAdd(sh + ST_BOUND + mode, bd);
+    if (pr) atomicAdd(sh + ST_PROBES + mode, pr);
+    if (mode == MODE_CORES) {
+      if (ev) atomicAdd(sh + ST_BUCKET_EVAL + k, ev);
+      if (pr) atomicAdd(sh + ST_BUCKET_PROBES + k, pr);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs B) {
+  __shared__ __align__(16) int32_t stage[(kBlock / 64) * kWaveSlots];
+  __shared__ unsigned long long sh_stats[ST_COUNT];
+  __shared__ unsigned long long s_item, s_cores;
+  __shared__ int64_t s_base, s_cnt;
+  __shared__ int32_t s_next;
+  const int tid = threadIdx.x;
+  int32_t* T = stage + (tid >> 6) * kWaveSlots;
+  for (int i = tid; i < ST_COUNT; i += kBlock) sh_stats[i] = 0;
+  const EdgeArgs& A = B.A;
+  while (true) {
+    if (tid == 0) {
+      s_item = batch_take(B);
+      s_cores = 0;
+    }
+    __syncthreads();
+    const unsigned long long item = s_item;
+    if (item == kBatchEmpty) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the graph's earlier phases
+    const int32_t g = (int32_t)(item >> 32);
+    const int ph = (int)((item >> 28) & 15u);
+    int64_t t = (int64_t)(item & 0x0FFFFFFFull);
+    const int64_t v0 = B.vtx_off[g], v1 = B.vtx_off[g + 1];
+    if (batch_vertex_phase(ph)) {
+      const int64_t b = v0 + t * B.tile_vertices;
+      const int64_t e = min(v1, b + (int64_t)B.tile_vertices);
+      bool core = false;
+      for (int64_t u = b + tid; u < e; u += kBlock) {
+        if (ph == BP_INIT) {
+          const int32_t mu = A.gmu[g];
+          const int64_t d = A.rp[u + 1] - A.rp[u];
+          A.lower[u] = 1;
+          A.upper[u] = (int32_t)(d + 1);
+          A.role[u] = (d + 1 < mu) ? ROLE_NONCORE : ROLE_UNK;
+          A.parent[u] = (int32_t)u;
+        } else if (ph == BP_FINAL) {
+          uint8_t r = ld_u8(A.role + u);
+          if (r == ROLE_UNK) {  // every edge of u was evaluated: lower is exact
+            r = A.lower[u] >= A.gmu[g] ? ROLE_CORE : ROLE_NONCORE;
+            st_u8(A.role + u, r);
+          }
+          core = core || r == ROLE_CORE;
+          if (r == ROLE_CORE) atomicAdd(&s_cores, 1ull);
+        } else if (ph == BP_FLAT) {
+          A.label[u] = ld_u8(A.role + u) == ROLE_CORE ? uf_find(A.parent, (int32_t)u) : INT_MAX;
+          if (B.split) A.upper[u] = -1;  // first cluster label seen (hub / outlier)
+        } else {  // BP_OUTPUT: graph-local labels
+          const int32_t lab = A.label[u];
+          const int32_t l = lab == INT_MAX ? INT_MAX : lab - (int32_t)v0;
+          const uint8_t r = A.role[u];
+          if (r == ROLE_CORE) {
+            B.out_roles[u] = 1;
+            B.out_labels[u] = l;
+          } else if (lab != INT_MAX) {
+            B.out_roles[u] = 2;
+            B.out_labels[u] = l;
+          } else {
+            B.out_roles[u] = B.split ? (r == ROLE_HUB ? 3 : 4) : 0;
+            B.out_labels[u] = -1;
+          }
+        }
+      }
+      (void)core;
+    } else {
+      // edge tile t: the bucket whose tiles hold it, and its edge range
+      int64_t lo[kNumBuckets], ek[kNumBuckets];
+      batch_graph_edges(B, g, lo, ek);
+      int k = 0;
+      for (; k < kNumBuckets; ++k) {
+        const int64_t tk = (ek[k] + B.tile_edges - 1) / B.tile_edges;
+        if (t < tk) break;
+        t -= tk;
+      }
+      const int64_t eb = k < kNumBuckets ? lo[k] + t * B.tile_edges : 0;
+      const int64_t ee = k < kNumBuckets ? min(lo[k] + ek[k], eb + (int64_t)B.tile_edges) : 0;
+      k = min(k, kNumBuckets - 1);  // (an item past the graph's tiles would be an empty range)
+      PassCounts pc;
+      if (ph == BP_CORES) {
+        for (int64_t e = eb + tid; e < ee; e += kBlock) A.state[e] = SIM_UNK;
+        __syncthreads();
+        batch_group<MODE_CORES>(B, k, eb, ee, T, pc);
+        batch_count(sh_stats, MODE_CORES, k, pc);
+      } else if (ph == BP_HOOK) {
+        for (int64_t e = eb + tid; e < ee; e += kBlock) {
+          if (A.state[e] != SIM_YES) continue;
+          const int2 uv = A.edges[e];
+          if (ld_u8(A.role + uv.x) == ROLE_CORE && ld_u8(A.role + uv.y) == ROLE_CORE) uf_union(A.parent, uv.x, uv.y);
+        }
+      } else if (ph == BP_MERGE) {
+        batch_group<MODE_MERGE>(B, k, eb, ee, T, pc);
+        batch_count(sh_stats, MODE_MERGE, k, pc);
+      } else if (ph == BP_ATTACH) {
+        batch_group<MODE_ATTACH>(B, k, eb, ee, T, pc);
+        batch_count(sh_stats, MODE_ATTACH, k, pc);
+      } else {  // BP_HUBOUT
+        for (int64_t e = eb + tid; e < ee; e += kBlock) {
+          const int2 uv = A.edges[e];
+          const int32_t lu = A.label[uv.x], lv = A.label[uv.y];
+          if ((lu == INT_MAX) == (lv == INT_MAX)) continue;
+          const int32_t x = (lu == INT_MAX) ? uv.x : uv.y;
+          const int32_t L = (lu == INT_MAX) ? lv : lu;
+          const int32_t seen = ld_i32(A.upper + x);
+          if (seen == L) continue;
+          const int32_t old = (seen == -1) ? atomicCAS(A.upper + x, -1, L) : seen;
+          if (old != -1 && old != L) st_u8(A.role + x, ROLE_HUB);
+        }
+      }
+    }
+    // release this tile's writes, then take it off the graph's phase count
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      s_cnt = 0;
+      if (ph == BP_FINAL && s_cores) atomicAdd(B.ncores + g, s_cores);
+      if (atomicSub(B.remaining + g, 1) == 1) {
+        // last tile of this phase: every other tile's writes are visible from here on
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const bool cores = __hip_atomic_load(B.ncores + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        int next = ph + 1;
+        int64_t cnt = 0, skipped = 0;
+        for (; next < BP_DONE; ++next) {
+          cnt = batch_tiles(B, g, next);
+          if (cnt > 0 && !cores && batch_phase_needs_cores(next)) {
+            skipped += cnt;
+            cnt = 0;
+          }
+          if (cnt > 0) break;
+        }
+        if (skipped) atomicAdd(B.ctl + 3, (unsigned long long)skipped);
+        if (next < BP_DONE) {
+          __hip_atomic_store(B.remaining + g, (int32_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_base = (int64_t)atomicAdd(B.ctl + 1, (unsigned long long)cnt);
+          s_cnt = cnt;
+          s_next = next;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_cnt > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the phase's writes and remaining[g] before the items
+      const int64_t base = s_base, cnt = s_cnt;
+      const int next = s_next;
+      for (int64_t i = tid; i < cnt; i += kBlock)
+        if (base + i < B.queue_cap)
+          __hip_atomic_store(B.queue + base + i, batch_item(g, next, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < ST_COUNT; i += kBlock)
+    if (sh_stats[i]) atomicAdd(A.stats + i, sh_stats[i]);
+}
+
+__global__ void k_batch_reset(BatchArgs B) {
+  const int64_t n = max(max(B.queue_cap, (int64_t)B.G), (int64_t)ST_COUNT);
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    if (i < B.queue_cap) B.queue[i] = kBatchEmpty;
+    if (i < B.G) {
+      B.remaining[i] = (int32_t)(B.init_prefix[i + 1] - B.init_prefix[i]);
+      B.ncores[i] = 0;
+    }
+    if (i < 4) B.ctl[i] = 0;
+    if (i < ST_COUNT) B.A.stats[i] = 0;
+  }
+}
+
+// eoff[k * (G + 1) + g] = first edge of bucket k whose larger side is at or
+// after vtx_off[g] (edges of a bucket are in increasing order of their larger
+// side, and graph g's vertices are vtx_off[g] .. vtx_off[g + 1] - 1).
+__global__ void k_batch_edge_offsets(int32_t G, const int64_t* vtx_off, const int2* edges, int64_t b0, int64_t b1,
+                                     int64_t* eoff) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > G) return;
+  const int64_t v = vtx_off[g];
+  int64_t lo = b0, hi = b1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)edges[mid].y < v) lo = mid + 1;
+    else hi = mid;
+  }
+  eoff[g] = (g == G) ? b1 : lo;
+}
+
 inline unsigned blocks_for(int64_t items, int64_t per_block, int64_t cap) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -1462,6 +1760,32 @@ void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int2* edges, 
   }
   k_output<<<blocks_for(n, 256, 1 << 30), 256, 0, s>>>(n, role, label, nullptr, nullptr, out_labels, out_roles,
                                                        split);
+}
+
+void launch_batch(hipStream_t s, const BatchArgs& B, int grid) {
+  const int64_t n = std::max<int64_t>(std::max<int64_t>(B.queue_cap, B.G), ST_COUNT);
+  k_batch_reset<<<blocks_for(n, 256, 16384), 256, 0, s>>>(B);
+  if (B.total > 0) k_batch<<<grid, kBlock, 0, s>>>(B);
+}
+
+void launch_batch_edge_offsets(hipStream_t s, int32_t G, const int64_t* vtx_off, const int2* edges,
+                               const int64_t* bucket_off_host, int64_t* eoff) {
+  for (int k = 0; k < kNumBuckets; ++k)
+    k_batch_edge_offsets<<<blocks_for((int64_t)G + 1, 256, 1 << 30), 256, 0, s>>>(
+        G, vtx_off, edges, bucket_off_host[k], bucket_off_host[k + 1], eoff + (int64_t)k * (G + 1));
+}
+
+int batch_grid_blocks() {
+  static int blocks = 0;  // the library drives one GPU
+  if (blocks == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch), kBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    blocks = per_cu * hub_grid_blocks();
+  }
+  return blocks;
 }
 
 }  // namespace scan

@@ -167,6 +167,74 @@ void launch_rethreshold(hipStream_t s, int32_t n, int64_t m, const int2* edges, 
                         uint8_t* role, int32_t* parent, int32_t* label, uint8_t* state,
                         int32_t* out_labels, uint8_t* out_roles, int32_t split);
 
+// ---------------------------------------------------------------------------
+// Batched clustering in one persistent launch (many graphs packed as one
+// disjoint union).  Every graph goes through the phases below in order; a
+// phase is cut into tiles (vertex tiles or edge tiles per degree bucket), and
+// blocks of the persistent kernel take (graph, phase, tile) items from a
+// device queue.  The block that finishes the last tile of a graph's phase
+// publishes the tiles of its next phase.
+enum BatchPhase : int {
+  BP_INIT = 0,  // bounds, roles, parents (vertex tiles)
+  BP_CORES,     // similarity test + core counting (edge tiles)
+  BP_FINAL,     // role finalize, cores counted per graph (vertex tiles)
+  BP_HOOK,      // union along known-similar core-core edges (edge tiles)
+  BP_MERGE,     // progressive core-core merge (edge tiles)
+  BP_FLAT,      // labels = roots (vertex tiles)
+  BP_ATTACH,    // border attachment (edge tiles)
+  BP_HUBOUT,    // hub / outlier marks, only with split roles (edge tiles)
+  BP_OUTPUT,    // graph-local labels and roles (vertex tiles)
+  BP_DONE
+};
+// Phases that have nothing to do for a graph without cores: their tiles are
+// never queued.
+__host__ __device__ inline bool batch_phase_needs_cores(int ph) {
+  return ph == BP_HOOK || ph == BP_MERGE || ph == BP_ATTACH || ph == BP_HUBOUT;
+}
+__host__ __device__ inline bool batch_vertex_phase(int ph) {
+  return ph == BP_INIT || ph == BP_FINAL || ph == BP_FLAT || ph == BP_OUTPUT;
+}
+// Tiles of phase ph for a graph of n vertices with ek[k] edges in bucket k.
+__host__ __device__ inline int64_t batch_phase_tiles(int ph, int64_t n, const int64_t* ek, int64_t tile_edges,
+                                                     int64_t tile_vertices, int split) {
+  if (ph == BP_HUBOUT && !split) return 0;
+  if (batch_vertex_phase(ph)) return (n + tile_vertices - 1) / tile_vertices;
+  int64_t t = 0;
+  for (int k = 0; k < kNumBuckets; ++k) t += (ek[k] + tile_edges - 1) / tile_edges;
+  return t;
+}
+
+struct BatchArgs {
+  EdgeArgs A;                    // graph arrays, per-vertex graph ids and per-graph eps/mu
+  int32_t G;
+  const int64_t* vtx_off;        // [G + 1] first vertex of each graph in the union
+  const int64_t* eoff;           // [kNumBuckets * (G + 1)]: first edge of graph g in bucket k
+  int32_t lanes[kNumBuckets];    // lane-group width per bucket (4, 8, 16, 32 or 64)
+  int32_t tile_edges;            // edges per edge tile (a multiple of 64)
+  int32_t tile_vertices;         // vertices per vertex tile
+  int32_t split;                 // hub / outlier roles
+  int32_t* out_labels;           // graph-local labels
+  uint8_t* out_roles;
+  unsigned long long* queue;     // items of every phase after BP_INIT (empty slots hold ~0)
+  const int64_t* init_prefix;    // [G + 1]: prefix of the graphs' BP_INIT tiles
+  int32_t* remaining;            // [G]: tiles of the graph's current phase not finished
+  unsigned long long* ncores;    // [G]
+  unsigned long long* ctl;       // [0] slots taken, [1] queue slots filled, [2] error, [3] items skipped
+  int64_t total;                 // items of the whole run if no phase is skipped
+  int64_t init_items;            // BP_INIT items (init_prefix[G])
+  int64_t queue_cap;             // queue slots
+  uint64_t watchdog_ticks;       // wall-clock ticks a block waits for an item before giving up
+};
+// Resets the queue and counters, then runs the whole batch (two kernels,
+// capturable).  grid = blocks of the persistent kernel.
+void launch_batch(hipStream_t s, const BatchArgs& B, int grid);
+// eoff for graphs with vertex offsets vtx_off over the bucketed edge list
+// (edges of each bucket in increasing order of their larger side).
+void launch_batch_edge_offsets(hipStream_t s, int32_t G, const int64_t* vtx_off, const int2* edges,
+                               const int64_t* bucket_off_host, int64_t* eoff);
+// Blocks of the persistent kernel that fit on the device at once.
+int batch_grid_blocks();
+
 // Layout (layout.hip)
 struct LayoutResult {
   int64_t bucket_off[kNumBuckets + 1];

@@ -1,0 +1,56 @@
+"""Full-size workloads against digests of the CPU oracle's results, written by
+tests/golden/make_golden.py (which calls only the oracle and the seeded
+generators).  Each test regenerates its input, checks the input's digest, and
+compares the GPU library's results digest for digest.
+
+- Chung-Lu n = 50,000,000 (exponent 2.1, mean degree 30, degree cap 1e6,
+  seed 3; about 708 M edges) on the partition-based path under a 4 GiB device
+  budget and on the in-memory path: labels and roles at (1/2, 10) and (1/10, 3),
+  and the per-arc closed counts (Def. 5.1, Lemma 5.1, Alg. 5).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import paper_2311_12281_amd as S
+from gpu_helpers import note
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from digest import counts_digest, csr_digest, result_digest  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        return json.load(fh)
+
+
+def test_chunglu_50m_partitioned_and_in_memory_match_oracle():
+    gold = _golden("chunglu_n50m_seed3.json")
+    t = time.perf_counter()
+    g = gg.chung_lu(gold["n"], gold["mean_deg"], gold["exponent"], gold["max_deg"], seed=gold["seed"])
+    note("chung-lu 50M generated", f"m={g.m}", f"{time.perf_counter() - t:.0f}s")
+    assert g.m == gold["m"] and csr_digest(g) == gold["csr_sha256"], "input differs from the one the oracle saw"
+    for budget in (4 << 30, 0):
+        t = time.perf_counter()
+        with S.Graph.from_csr(g, budget=budget) as G:
+            note("chung-lu 50M", f"budget={budget}", f"created in {time.perf_counter() - t:.0f}s")
+            for run in gold["runs"]:
+                (p, q), mu = run["eps"], run["mu"]
+                t = time.perf_counter()
+                labels, roles = G.run(p, q, mu)
+                note(f"budget={budget} eps={p}/{q} mu={mu}", f"{time.perf_counter() - t:.2f}s",
+                     f"cores={int((roles == 1).sum())}")
+                assert int((roles == 1).sum()) == run["cores"] and int((roles == 2).sum()) == run["borders"]
+                assert result_digest(labels, roles) == run["result_sha256"], f"budget={budget} eps={p}/{q} mu={mu}"
+                del labels, roles
+            counts = G.similarity()
+            assert counts_digest(counts) == gold["counts_sha256"], f"budget={budget}: closed counts differ"
+            del counts

@@ -67,3 +67,57 @@ def test_partitioned_budget_errors():
     with pytest.raises(S.ScanError) as ei:
         S.scan_graph_create(3, 2, bad_rp, bad_ci, S.make_opts(budget=64))
     assert ei.value.code in (S.SCAN_E_GRAPH, S.SCAN_E_NOMEM)
+
+
+def _hub_graph_budget(g, blocks):
+    """A budget whose row buffer holds the largest row but about 1/blocks of
+    the arcs per block, so the rows are streamed in several blocks."""
+    n, nnz = g.n, g.nnz
+    resident = 8 * (n + 1) + 22 * n + (1 << 20)
+    maxdeg = int(g.degrees().max())
+    blk = max(maxdeg + 1, nnz // blocks)
+    # part of the budget after the resident state: a quarter for the chunk
+    # buffers, the rest for a row buffer of two blocks (8 bytes per block arc)
+    rest = int(blk * 8 / 0.75) + 4096
+    return resident + rest
+
+
+@pytest.mark.parametrize("name", ["windowed-hub", "spread-hub", "bitmap-edge"])
+def test_partitioned_hub_windows_in_a_later_block(name):
+    """Hub rows that the LDS-hash kernel takes as several hash and bitmap
+    windows, streamed as block rows: the graphs of the in-memory window tests
+    with their ids reversed, so that the hub is the last vertex and its row
+    sits in the last block, shifted in the device row buffer."""
+    import test_gpu_parity as tp
+
+    gen = {"windowed-hub": tp.windowed_hub_graph, "spread-hub": tp.spread_hub_graph,
+           "bitmap-edge": tp.bitmap_edge_graph}[name]
+    g = gg.reverse_ids(gen())
+    budget = _hub_graph_budget(g, 4)
+    note("partitioned hub windows", name, f"n={g.n} m={g.m} budget={budget}")
+    oc = oracle.counts(g, threads=oracle.max_threads())
+    params = [((1, 10), 2), ((1, 5), 3), ((1, 16), 3), ((1, 40), 2)]
+    for ranked in (True, False):
+        with S.Graph.from_csr(g, budget=budget, hub_ranked=ranked) as P:
+            assert np.array_equal(P.similarity(), oc), f"{name}: partitioned counts differ"
+            assert P.stats()["h2d_bytes"] > g.nnz * 4  # rows were streamed
+            for (p, q), mu in params:
+                gl, gr = P.run(p, q, mu)
+                ol, orr = oracle.cluster(g, oc, p, q, mu)
+                assert_same(gl, gr, ol, orr, f"partitioned {name} eps={p}/{q} mu={mu}")
+
+
+def test_partitioned_chung_lu_with_large_hubs():
+    """Chung-Lu with degrees up to 20,000 (hub rows of several LDS windows)
+    under a budget of a few blocks."""
+    g = gg.chung_lu(400000, 30.0, 2.1, 20000.0, seed=8)
+    assert int(g.degrees().max()) > 2 * 4096
+    budget = _budget_for(g, 0.12)
+    note("partitioned chung-lu large hubs", f"m={g.m} budget={budget}")
+    oc = oracle.counts(g, threads=oracle.max_threads())
+    with S.Graph.from_csr(g, budget=budget) as P:
+        assert np.array_equal(P.similarity(), oc)
+        for (p, q), mu in [((1, 10), 3), ((1, 5), 4), ((1, 2), 2)]:
+            gl, gr = P.run(p, q, mu)
+            ol, orr = oracle.cluster(g, oc, p, q, mu)
+            assert_same(gl, gr, ol, orr, f"partitioned chung-lu-400k eps={p}/{q} mu={mu}")
