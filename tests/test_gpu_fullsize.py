@@ -7,6 +7,10 @@ compares the GPU library's results digest for digest.
   seed 3; about 708 M edges) on the partition-based path under a 4 GiB device
   budget and on the in-memory path: labels and roles at (1/2, 10) and (1/10, 3),
   and the per-arc closed counts (Def. 5.1, Lemma 5.1, Alg. 5).
+- 10,000 planted-partition graphs (n log-uniform in [100, 20000], mean degree
+  U[8, 64], 5-200 blocks, per-graph eps in {1/5, 2/5, 3/5, 4/5} and mu in
+  2..10, seed 4; about 677 M edges in all) clustered in one persistent batched
+  run: every graph's labels and roles.
 """
 import json
 import os
@@ -54,3 +58,27 @@ def test_chunglu_50m_partitioned_and_in_memory_match_oracle():
             counts = G.similarity()
             assert counts_digest(counts) == gold["counts_sha256"], f"budget={budget}: closed counts differ"
             del counts
+
+
+def test_planted_batch_10000_matches_oracle():
+    gold = _golden("planted_batch_10000_seed4.json")
+    t = time.perf_counter()
+    graphs, specs = gg.planted_batch(gold["count"], seed=gold["seed"])
+    import hashlib
+    h = hashlib.sha256()
+    for g in graphs:
+        h.update(bytes.fromhex(csr_digest(g)))
+    note("planted batch generated", len(graphs), f"{time.perf_counter() - t:.0f}s")
+    assert h.hexdigest() == gold["csr_sha256_of_digests"], "inputs differ from the ones the oracle saw"
+    eps = [s.eps for s in specs]
+    mus = [s.mu for s in specs]
+    assert [list(e) for e in eps] == gold["eps"] and mus == gold["mu"]
+    t = time.perf_counter()
+    with S.Batch(graphs, eps, mus) as B:
+        note("batch created", f"{time.perf_counter() - t:.0f}s")
+        for rep in range(2):
+            labels, roles = B.run(replay=True)
+            note("batch run", rep, f"{B.stats()['ms_total']:.1f} ms")
+            bad = [k for k, (l, r) in enumerate(zip(B.split(labels), B.split(roles)))
+                   if result_digest(l, r)[:12] != gold["result_sha256_12"][k]]
+            assert not bad, f"{len(bad)} graphs differ from the oracle, first {bad[:10]}"
