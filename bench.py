@@ -63,11 +63,13 @@ def main():
     ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched"])
     ap.add_argument("--cl-n", type=int, default=50_000_000, help="partitioned: Chung-Lu vertices")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="partitioned: device budget")
-    ap.add_argument("--serve-graphs", type=int, default=16)
-    ap.add_argument("--serve-scale-min", type=int, default=14)
-    ap.add_argument("--serve-scale-max", type=int, default=20)
-    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-graphs", type=int, default=64, help="serving: resident R-MAT graphs")
+    ap.add_argument("--serve-uploads", type=int, default=8, help="serving: graphs added during the stream")
+    ap.add_argument("--serve-upload-every", type=float, default=1.0, help="serving: seconds between uploads")
+    ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-plain-seconds", type=float, default=10.0,
+                    help="serving: arrivals of the plain comparison (bounded run)")
     ap.add_argument("--batch-count", type=int, default=10000)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy calibration")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -389,112 +391,197 @@ def bench_partitioned(args):
 
 
 def bench_serving(args):
-    """Resident R-MAT graphs; a Poisson stream of (graph, eps = k/10, mu)
-    queries at a fixed rate.  Served: cached closed counts, re-thresholding,
-    continuous batching over slots.  Plain: one scan_run per query, first come
-    first served.  Latency = completion - arrival."""
+    """Resident R-MAT graphs (scale 16..23, edge factor 8..32) plus uploads
+    added while the queries run; a Poisson stream of (graph, eps = k/10,
+    mu) queries at 0.5x and 0.9x of the served path's saturation rate.
+    Served: cached closed counts, re-thresholding, continuous batching over
+    slots, memory admission (an upload that does not fit stays on the host
+    and its queries take the partition-based path on the fallback thread).
+    Plain: one scan_run per query on resident graphs, first come first served,
+    at the same arrivals.  Latency = completion - arrival.  Exactness: the
+    stored oracle digests of two queries per graph, and every query of the
+    Poisson runs against the same query run alone afterwards."""
+    import hashlib
     import threading
 
     import graphgen as gg
     import paper_2311_12281_amd as S
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from digest import result_digest
 
-    rng = np.random.default_rng(5)
-    graphs = []
-    for k in range(args.serve_graphs):
-        sc = int(rng.integers(args.serve_scale_min, args.serve_scale_max + 1))
-        ef = int(rng.integers(8, 33))
-        graphs.append(gg.rmat(sc, ef, seed=100 + k))
-    log(f"{len(graphs)} R-MAT graphs, {sum(g.m for g in graphs)} edges in total")
-    queries = [(int(rng.integers(len(graphs))), int(rng.integers(1, 10)), 10, int(rng.integers(2, 21)))
-               for _ in range(args.serve_queries)]
-    srv = S.Server(num_slots=args.serve_slots)
+    res_specs, up_specs = gg.serving_specs(count=args.serve_graphs, uploads=args.serve_uploads, seed=5)
+    t = time.perf_counter()
+    graphs = [sp.make() for sp in res_specs]
+    uploads = [sp.make() for sp in up_specs]
+    log(f"{len(graphs)} resident + {len(uploads)} upload R-MAT graphs, {sum(g.m for g in graphs)} + "
+        f"{sum(g.m for g in uploads)} edges, generated in {time.perf_counter() - t:.0f}s")
+    nslots = args.serve_slots
+    served_bytes = lambda g: S.scan_graph_footprint(g.n, g.nnz, S.make_opts()) + 12 * g.m  # noqa: E731
+    slot_bytes = nslots * max(18 * g.n + g.m for g in graphs + uploads)
+    # budget: every resident graph and all uploads but the last fit (its queries use the fallback)
+    budget = sum(served_bytes(g) for g in graphs + uploads[:-1]) + slot_bytes + (64 << 20)
+    srv = S.Server(num_slots=nslots, budget=budget)
     t = time.perf_counter()
     gids = [srv.add(g) for g in graphs]
     add_s = time.perf_counter() - t
-    plain = [S.Graph.from_csr(g) for g in graphs]
+    log(f"added {len(gids)} graphs in {add_s:.1f}s; budget {budget / 2**30:.1f} GiB, held "
+        f"{srv.info()['resident_bytes'] / 2**30:.1f} GiB")
+    all_graphs = graphs + uploads
+    rng = np.random.default_rng(7)
+    nq = args.serve_queries
+    picks = rng.random(nq)
+    eps_k = rng.integers(1, 10, size=nq)
+    mus = rng.integers(2, 21, size=nq)
 
-    def served_saturation():
-        t0 = time.perf_counter()
-        reqs = [srv.submit(gids[gi], p, q, mu) for gi, p, q, mu in queries]
-        for r, (gi, _, _, _) in zip(reqs, queries):
-            srv.wait(r, gids[gi])
-        return len(queries) / (time.perf_counter() - t0)
+    def query(k, ngraphs):
+        return int(picks[k] * ngraphs), int(eps_k[k]), 10, int(mus[k])
 
-    def plain_saturation():
-        t0 = time.perf_counter()
-        for gi, p, q, mu in queries[:200]:
-            plain[gi].run(p, q, mu)
-        return 200 / (time.perf_counter() - t0)
+    # saturation: the whole query list on the resident graphs, submitted at once
+    t0 = time.perf_counter()
+    reqs = [(srv.submit(gids[gi], p, q, mu), gi) for gi, p, q, mu in (query(k, len(gids)) for k in range(nq))]
+    sat_edges = 0.0
+    for r, gi in reqs:
+        srv.wait(r, gids[gi])
+        sat_edges += graphs[gi].m
+    sat_s = time.perf_counter() - t0
+    sat = nq / sat_s
+    log(f"served saturation: {sat:.0f} queries/s, {sat_edges / sat_s / 1e9:.2f} G edges/s")
 
-    sat_served = served_saturation()
-    sat_plain = plain_saturation()
-    log(f"saturation: served {sat_served:.1f} q/s, plain {sat_plain:.1f} q/s")
+    res_gids = list(gids)       # graphs queries may target (resident ones and uploads that became resident)
+    upload_gids = []
 
-    def run_served(qps):
-        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(queries)))
-        lat = [0.0] * len(queries)
-        reqs = [None] * len(queries)
-        start = time.perf_counter()
+    def run_served(qps, with_uploads):
+        arr = np.cumsum(np.random.default_rng(int(qps)).exponential(1.0 / qps, size=nq))
+        lat = [0.0] * nq
+        dig = [None] * nq
+        keys = [None] * nq
         ready = threading.Semaphore(0)
+        start = time.perf_counter()
 
         def waiter():
-            for k in range(len(queries)):
+            for k in range(nq):
                 ready.acquire()
-                _, _, ms = srv.wait(reqs[k], gids[queries[k][0]])
+                r, gid = keys[k][0], keys[k][1]
+                lab, rol, ms = srv.wait(r, gid)
                 lat[k] = ms
+                dig[k] = result_digest(lab, rol)
+
+        def uploader():
+            for j, g in enumerate(uploads):
+                d = start + (j + 1) * args.serve_upload_every - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                gid = srv.add(g)
+                g_index[gid] = len(graphs) + j
+                upload_gids.append(gid)
+                if srv.info()["resident_graphs"] == len(res_gids) + 1:
+                    res_gids.append(gid)
 
         th = threading.Thread(target=waiter)
         th.start()
-        for k, (gi, p, q, mu) in enumerate(queries):
+        up = threading.Thread(target=uploader) if with_uploads else None
+        if up:
+            up.start()
+        for k in range(nq):
             d = start + arr[k] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            reqs[k] = srv.submit(gids[gi], p, q, mu)
+            pool = list(res_gids)
+            gi, p, q, mu = query(k, len(pool))
+            gid = pool[gi]
+            keys[k] = (srv.submit(gid, p, q, mu), gid, p, q, mu)
             ready.release()
         th.join()
+        if up:
+            up.join()
         wall = time.perf_counter() - start
-        return np.array(lat), wall
+        lat = np.array(lat)
+        # latency from arrival: the submit happens at the arrival (to within the sleep's precision)
+        edges = float(sum(all_graphs[g_index[key[1]]].m for key in keys))
+        return lat, wall, edges, keys, dig
 
-    def run_plain(qps, count):
-        arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
+    g_index = {gid: i for i, gid in enumerate(gids)}
+    out = {}
+    checks = []
+    for frac in (0.5, 0.9):
+        qps = frac * sat
+        with_up = frac == 0.5
+        lat, wall, edges, keys, dig = run_served(qps, with_up)
+        checks += [(k[1], k[2], k[3], k[4], d) for k, d in zip(keys, dig)]
+        out[f"{frac}x"] = {"qps": qps, "queries": nq, "served_p50_ms": float(np.percentile(lat, 50)),
+                           "served_p99_ms": float(np.percentile(lat, 99)), "served_edges_per_s": edges / wall,
+                           "served_wall_s": wall}
+        log(f"served {frac}x: {out[f'{frac}x']}")
+    info = srv.info()
+    log(f"server: {info}")
+    # the upload kept on the host: its queries take the partition-based path
+    fb_gid = [gid for gid in upload_gids if gid not in res_gids]
+    fallback = None
+    if fb_gid:
+        gid = fb_gid[0]
+        ms = [srv.wait(srv.submit(gid, k, 10, 5), gid)[2] for k in (3, 5, 7)]
+        fallback = {"graph_edges": all_graphs[g_index[gid]].m, "latency_ms": ms}
+        log(f"fallback queries: {fallback}")
+
+    # plain: one scan_run per query, resident graphs, same arrival process, bounded count
+    plain_graphs = {gid: S.Graph.from_csr(all_graphs[g_index[gid]]) for gid in res_gids}
+    for frac in (0.5, 0.9):
+        qps = frac * sat
+        cnt = min(nq, max(100, int(qps * args.serve_plain_seconds)))
+        arr = np.cumsum(np.random.default_rng(int(qps)).exponential(1.0 / qps, size=cnt))
         lat = []
+        edges = 0.0
         start = time.perf_counter()
-        for k, (gi, p, q, mu) in enumerate(queries[:count]):
+        for k in range(cnt):
             d = start + arr[k] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            plain[gi].run(p, q, mu)
+            gi, p, q, mu = query(k, len(res_gids))
+            gid = res_gids[gi]
+            plain_graphs[gid].run(p, q, mu)
             lat.append((time.perf_counter() - start - arr[k]) * 1e3)
-        return np.array(lat), time.perf_counter() - start
-
-    out = {}
-    edges = float(sum(graphs[gi].m for gi, _, _, _ in queries))
-    for frac in (0.5, 0.9):
-        qps = frac * sat_served
-        ls, ws = run_served(qps)
-        cnt = min(len(queries), max(50, int(qps * 10)))  # plain path: bounded run at the same rate
-        lp, wp = run_plain(qps, cnt)
-        out[f"{frac}x"] = {
-            "qps": qps,
-            "served_p50_ms": float(np.percentile(ls, 50)), "served_p99_ms": float(np.percentile(ls, 99)),
-            "served_edges_per_s": edges / ws,
-            "plain_p50_ms": float(np.percentile(lp, 50)), "plain_p99_ms": float(np.percentile(lp, 99)),
-            "plain_edges_per_s": float(sum(graphs[gi].m for gi, _, _, _ in queries[:cnt])) / wp,
-            "plain_queries": cnt}
-        log(f"{frac}x: {out[f'{frac}x']}")
-    # exactness: served answers equal scan_run for a sample
-    exact = True
-    for gi, p, q, mu in queries[:50]:
-        l, r, _ = srv.wait(srv.submit(gids[gi], p, q, mu), gids[gi])
-        gl, gr = plain[gi].run(p, q, mu)
-        exact = exact and bool(np.array_equal(l, gl) and np.array_equal(r, gr))
-    for G in plain:
+            edges += all_graphs[g_index[gid]].m
+        wall = time.perf_counter() - start
+        o = out[f"{frac}x"]
+        o.update({"plain_queries": cnt, "plain_p50_ms": float(np.percentile(lat, 50)),
+                  "plain_p99_ms": float(np.percentile(lat, 99)), "plain_edges_per_s": edges / wall})
+        log(f"plain {frac}x: p50 {o['plain_p50_ms']:.1f} ms p99 {o['plain_p99_ms']:.1f} ms "
+            f"{o['plain_edges_per_s'] / 1e9:.2f} G edges/s over {cnt} queries")
+    for G in plain_graphs.values():
         G.close()
+
+    # exactness 1: two stored oracle results per graph (64 resident + uploads)
+    gold_path = os.path.join(ROOT, "tests", "golden", "serving_rmat72_seed5.json")
+    oracle_ok = None
+    if os.path.exists(gold_path) and args.serve_graphs == 64 and args.serve_uploads == 8:
+        import json as _json
+        with open(gold_path) as fh:
+            gold = _json.load(fh)
+        oracle_ok = True
+        all_gids = gids + upload_gids
+        for i, gr in enumerate(gold["graphs"]):
+            gid = all_gids[i]
+            for run in gr["runs"]:
+                (p, q), mu = run["eps"], run["mu"]
+                lab, rol, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
+                oracle_ok = oracle_ok and result_digest(lab, rol) == run["result_sha256"]
+        log(f"oracle digests ({sum(len(gr['runs']) for gr in gold['graphs'])} queries): {oracle_ok}")
+    # exactness 2: every query of the Poisson runs equals the same query alone
+    alone = {}
+    alone_ok = True
+    for gid, p, q, mu, d in checks:
+        key = (gid, p, q, mu)
+        if key not in alone:
+            lab, rol, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
+            alone[key] = result_digest(lab, rol)
+        alone_ok = alone_ok and alone[key] == d
+    log(f"every query equals its alone-run: {alone_ok} ({len(checks)} queries, {len(alone)} distinct)")
     srv.close()
-    _line("queries/s at saturation, served (cached counts, continuous batching)", sat_served, "queries/s",
-          {"workload": f"serving_{len(graphs)}_rmat_s{args.serve_scale_min}-{args.serve_scale_max}",
-           "queries": len(queries), "slots": args.serve_slots},
-          plain_saturation_qps=sat_plain, add_graphs_s=add_s, exact_match=exact, poisson=out)
+    _line("queries/s at saturation, served (cached counts, continuous batching)", sat, "queries/s",
+          {"workload": f"serving_rmat{len(graphs)}+{len(uploads)}_s16-23_ef8-32", "resident_graphs": len(graphs),
+           "uploads": len(uploads), "queries": nq, "slots": nslots, "budget_bytes": budget},
+          saturation_edges_per_s=sat_edges / sat_s, add_graphs_s=add_s, oracle_digests_exact=oracle_ok,
+          alone_run_exact=alone_ok, fallback=fallback, poisson=out)
 
 
 def bench_batched(args):

@@ -43,7 +43,7 @@ namespace {
 
 void release(scan_graph* g) {
   part_release(g);
-  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_jobs, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -95,6 +95,7 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   A.ci = g->d_ci;
   A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
+  A.wtab = g->d_wtab;
   A.state = R.state;
   A.lower = R.lower;
   A.upper = R.upper;
@@ -178,7 +179,8 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   if (g->partitioned) return 0;
   const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, m = (uint64_t)g->m;
   const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
-  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6;
+  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
+               4 * (uint64_t)g->wtab_entries;
   if (g->d_hci) b += 4 * (nnz + kColPad);
   b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
   if (g->d_out_labels) b += 5 * n;
@@ -230,6 +232,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   A.ci = g->d_ci;
   A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
+  A.wtab = g->d_wtab;
   A.counts = d_counts_arc;
   A.edge_counts = d_counts_edge;
   A.stats = g->d_stats;
@@ -299,6 +302,9 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
   int rc = SCAN_OK;
   hipError_t e;
   LayoutResult lay{};
+  std::vector<HubJob> jobs;
+  std::vector<uint32_t> wtab;
+  std::vector<int32_t> ranked;
 #define CTRY(call, what)                         \
   do {                                           \
     e = (call);                                  \
@@ -342,7 +348,7 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     CTRY(hipMemcpyAsync(g->d_ci, col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, g->stream),
          "copy col_idx");
   CTRY(build_layout(g->stream, n, nnz, row_ptr, col_idx, g->d_rp, g->d_ci, g->opts.validate, &g->d_edges,
-                    &g->d_jobs, &lay), "layout");
+                    &jobs, &lay), "layout");
   if (lay.error) {
     rc = fail(SCAN_E_GRAPH, "CSR rejected (flags 0x%x: 1 offsets, 2 id range, 4 self-loop, "
               "8 row order/duplicate, 16 missing reverse arc, 32 inconsistent layout)", lay.error);
@@ -352,7 +358,20 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
   g->hub_jobs = lay.hub_jobs;
   if (g->opts.hub_ranked && n > kHubBitmapBits && lay.hub_jobs > 0) {
     CTRY(dalloc(&g->d_hci, nnz + kColPad), "hipMalloc ranked rows");
-    CTRY(build_ranked_rows(g->stream, n, nnz, row_ptr, col_idx, g->d_hci), "ranked rows");
+    CTRY(build_ranked_rows(g->stream, n, nnz, row_ptr, col_idx, g->d_hci, &ranked), "ranked rows");
+  }
+  if (!jobs.empty()) {
+    // LDS-hash windows of every hub row, from the rows the kernel reads
+    assign_hub_windows(jobs, row_ptr, g->d_hci ? ranked.data() : col_idx, wtab);
+    std::vector<int32_t>().swap(ranked);
+    CTRY(dalloc(&g->d_jobs, (int64_t)jobs.size()), "hipMalloc jobs");
+    CTRY(dalloc(&g->d_wtab, (int64_t)wtab.size()), "hipMalloc windows");
+    CTRY(hipMemcpyAsync(g->d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice, g->stream),
+         "copy jobs");
+    CTRY(hipMemcpyAsync(g->d_wtab, wtab.data(), sizeof(uint32_t) * wtab.size(), hipMemcpyHostToDevice, g->stream),
+         "copy windows");
+    CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    g->wtab_entries = (int64_t)wtab.size();
   }
   for (int k = 0; k <= kNumBuckets; ++k) g->bucket_off[k] = lay.bucket_off[k];
   g->m = lay.bucket_off[kNumBuckets];

@@ -49,7 +49,7 @@ struct scan_batch_graph {
   int32_t* d_labels = nullptr;
   uint8_t* d_roles = nullptr;
   int32_t lanes[kNumBuckets] = {4, 8, 16, 32, 64, 64, 64};
-  int32_t tile_edges = 1024;
+  int32_t tile_edges = 4096;
   int grid = 0;
   BatchArgs args{};
   hipGraph_t graph = nullptr;
@@ -61,9 +61,9 @@ struct scan_batch_graph {
 
 namespace {
 
-constexpr int32_t kTileVertices = 1024;
-constexpr int32_t kTileEdgeChoices[] = {512, 1024, 2048, 4096};
-constexpr int32_t kMinTileEdges = 512;
+constexpr int32_t kTileVertices = 4096;
+constexpr int32_t kTileEdgeChoices[] = {1024, 2048, 4096, 8192, 16384};
+constexpr int32_t kMinTileEdges = 1024;
 
 void batch_release(scan_batch_graph* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
@@ -128,7 +128,12 @@ int batch_prepare(scan_batch_graph* B) {
   P.G = B->G;
   P.vtx_off = B->d_vtx_off;
   P.eoff = B->d_eoff;
-  for (int k = 0; k < kNumBuckets; ++k) P.lanes[k] = B->lanes[k];
+  P.lanes_code = 0;
+  for (int k = 0; k < kNumBuckets; ++k) {
+    uint32_t c = 0;
+    while ((4 << c) < B->lanes[k]) ++c;
+    P.lanes_code |= c << (3 * k);
+  }
   P.tile_edges = B->tile_edges;
   P.tile_vertices = kTileVertices;
   P.split = g->opts.hub_outlier ? 1 : 0;

@@ -40,6 +40,7 @@ struct PartPlan {
   uint8_t* d_state2 = nullptr;
   int32_t* d_ecount = nullptr;
   HubJob* d_jobs = nullptr;       // every chunk's LDS-hash jobs (resident)
+  uint32_t* d_wtab = nullptr;     // their windows
   int32_t* d_worklist = nullptr;  // one slot per edge of a chunk
   unsigned long long* d_jobctr = nullptr;
   hipStream_t copy = nullptr;     // upload stream (default priority)
@@ -66,6 +67,8 @@ struct scan_graph {
   int2* d_edges = nullptr;
   HubJob* d_jobs = nullptr;
   int64_t hub_jobs = 0;
+  uint32_t* d_wtab = nullptr;     // LDS-hash windows of the jobs' larger sides
+  int64_t wtab_entries = 0;
   int32_t* d_worklist = nullptr;  // one slot per edge of the last bucket
   // per-run state
   int32_t* d_lower = nullptr;

@@ -804,16 +804,28 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
     const int32_t S = s_n;
     const int64_t bv = row_start(A, J.v);
     const int64_t dv = A.rp[J.v + 1] - A.rp[J.v];
+    // v's windows as computed when the graph was created (the first
+    // kHubMaxWindows of them); any further ones are found below as they come
+    int32_t n_known = 0;  // windows of this job in s_wend / s_wbitmap
+    if (S > 0 && J.wcnt > 0) {
+      n_known = min(J.wcnt, kHubMaxWindows);
+      for (int k = tid; k < n_known; k += kHubBlock) {
+        const uint32_t w = A.wtab[J.wbeg + k];
+        s_wend[k] = (int64_t)(w >> 1);
+        s_wbitmap[k] = (uint8_t)(w & 1u);
+      }
+      __syncthreads();
+    }
     // Start of the longest suffix of nbr(v) that one bitmap covers; when it
     // holds at least kHubBitmapMin elements, hash windows stop at it, so that
-    // the suffix becomes a single bitmap window.
+    // the suffix becomes a single bitmap window.  (Needed only to find windows
+    // here.)
     int64_t wsuf = dv;
-    if (S > 0 && dv >= kHubBitmapMin) {
+    if (S > 0 && dv >= kHubBitmapMin && (J.wcnt <= 0 || J.wcnt > kHubMaxWindows)) {
       const int64_t T = (int64_t)A.hci[bv + dv - 1] - kHubBitmapBits + 1;
       const int64_t ws = ((int64_t)A.hci[bv] >= T) ? 0 : block_find(A.hci + bv, 0, dv, T, &s_first);
       if (dv - ws >= kHubBitmapMin) wsuf = ws;
     }
-    int32_t n_known = 0;  // windows of this job in s_wend / s_wbitmap
     // Phase B
     for (int32_t b0 = 0; b0 < S; b0 += kHubBatch) {
       const int32_t nbatch = (S - b0 < kHubBatch) ? S - b0 : kHubBatch;
@@ -1359,7 +1371,7 @@ __device__ __forceinline__ int64_t batch_tiles(const BatchArgs& B, int32_t g, in
 
 // Thread 0: claims the next slot and returns its item, or kBatchEmpty when
 // the run is over (or was abandoned).
-__device__ unsigned long long batch_take(const BatchArgs& B) {
+__device__ __forceinline__ unsigned long long batch_take(const BatchArgs& B) {
   const unsigned long long slot = atomicAdd(B.ctl + 0, 1ull);
   if ((int64_t)slot >= B.total) return kBatchEmpty;
   if ((int64_t)slot < B.init_items) {
@@ -1393,7 +1405,7 @@ __device__ __forceinline__ void batch_group(const BatchArgs& B, int k, int64_t l
                                             PassCounts& pc) {
   const int64_t wave = threadIdx.x >> 6;
   constexpr int64_t nw = kBlock / 64;
-  switch (B.lanes[k]) {
+  switch (4 << ((B.lanes_code >> (3 * k)) & 7u)) {
     case 4: group_edges<MODE, 4, false>(B.A, lo, hi, wave, nw, T, pc); break;
     case 8: group_edges<MODE, 8, false>(B.A, lo, hi, wave, nw, T, pc); break;
     case 16: group_edges<MODE, 16, false>(B.A, lo, hi, wave, nw, T, pc); break;
@@ -1419,7 +1431,9 @@ __device__ __forceinline__ void batch_count(unsigned long long* sh, int mode, in
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs B) {
+// Six waves per SIMD: the intersections of the small buckets wait on global
+// memory, so occupancy pays for the few registers spilled.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch(BatchArgs B) {
   __shared__ __align__(16) int32_t stage[(kBlock / 64) * kWaveSlots];
   __shared__ unsigned long long sh_stats[ST_COUNT];
   __shared__ unsigned long long s_item, s_cores;
@@ -1438,9 +1452,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs B) {
     const unsigned long long item = s_item;
     if (item == kBatchEmpty) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the graph's earlier phases
-    const int32_t g = (int32_t)(item >> 32);
-    const int ph = (int)((item >> 28) & 15u);
-    int64_t t = (int64_t)(item & 0x0FFFFFFFull);
+    // uniform over the block: kept in scalar registers
+    const int32_t g = __builtin_amdgcn_readfirstlane((int32_t)(item >> 32));
+    const int ph = __builtin_amdgcn_readfirstlane((int)((item >> 28) & 15u));
+    const int64_t t = __builtin_amdgcn_readfirstlane((int32_t)(item & 0x0FFFFFFFull));
     const int64_t v0 = B.vtx_off[g], v1 = B.vtx_off[g + 1];
     if (batch_vertex_phase(ph)) {
       const int64_t b = v0 + t * B.tile_vertices;
@@ -1483,47 +1498,48 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs B) {
       }
       (void)core;
     } else {
-      // edge tile t: the bucket whose tiles hold it, and its edge range
-      int64_t lo[kNumBuckets], ek[kNumBuckets];
-      batch_graph_edges(B, g, lo, ek);
-      int k = 0;
-      for (; k < kNumBuckets; ++k) {
-        const int64_t tk = (ek[k] + B.tile_edges - 1) / B.tile_edges;
-        if (t < tk) break;
-        t -= tk;
-      }
-      const int64_t eb = k < kNumBuckets ? lo[k] + t * B.tile_edges : 0;
-      const int64_t ee = k < kNumBuckets ? min(lo[k] + ek[k], eb + (int64_t)B.tile_edges) : 0;
-      k = min(k, kNumBuckets - 1);  // (an item past the graph's tiles would be an empty range)
-      PassCounts pc;
-      if (ph == BP_CORES) {
-        for (int64_t e = eb + tid; e < ee; e += kBlock) A.state[e] = SIM_UNK;
-        __syncthreads();
-        batch_group<MODE_CORES>(B, k, eb, ee, T, pc);
-        batch_count(sh_stats, MODE_CORES, k, pc);
-      } else if (ph == BP_HOOK) {
-        for (int64_t e = eb + tid; e < ee; e += kBlock) {
-          if (A.state[e] != SIM_YES) continue;
-          const int2 uv = A.edges[e];
-          if (ld_u8(A.role + uv.x) == ROLE_CORE && ld_u8(A.role + uv.y) == ROLE_CORE) uf_union(A.parent, uv.x, uv.y);
-        }
-      } else if (ph == BP_MERGE) {
-        batch_group<MODE_MERGE>(B, k, eb, ee, T, pc);
-        batch_count(sh_stats, MODE_MERGE, k, pc);
-      } else if (ph == BP_ATTACH) {
-        batch_group<MODE_ATTACH>(B, k, eb, ee, T, pc);
-        batch_count(sh_stats, MODE_ATTACH, k, pc);
-      } else {  // BP_HUBOUT
-        for (int64_t e = eb + tid; e < ee; e += kBlock) {
-          const int2 uv = A.edges[e];
-          const int32_t lu = A.label[uv.x], lv = A.label[uv.y];
-          if ((lu == INT_MAX) == (lv == INT_MAX)) continue;
-          const int32_t x = (lu == INT_MAX) ? uv.x : uv.y;
-          const int32_t L = (lu == INT_MAX) ? lv : lu;
-          const int32_t seen = ld_i32(A.upper + x);
-          if (seen == L) continue;
-          const int32_t old = (seen == -1) ? atomicCAS(A.upper + x, -1, L) : seen;
-          if (old != -1 && old != L) st_u8(A.role + x, ROLE_HUB);
+      // edge tile t: edges t * tile_edges .. of the graph's bucket ranges
+      // taken one after the other; each bucket's part with its own lanes
+      const int64_t tb = t * B.tile_edges, te = tb + B.tile_edges;
+      int64_t pos = 0;  // position of bucket k's first edge in the concatenation
+      for (int k = 0; k < kNumBuckets; ++k) {
+        const int64_t* row = B.eoff + (int64_t)k * (B.G + 1);
+        const int64_t lo = row[g], ek = row[g + 1] - lo;
+        const int64_t at = pos;
+        pos += ek;
+        if (at + ek <= tb || at >= te) continue;
+        const int64_t eb = lo + max(tb - at, (int64_t)0);
+        const int64_t ee = lo + min(te - at, ek);
+        PassCounts pc;
+        if (ph == BP_CORES) {
+          for (int64_t e = eb + tid; e < ee; e += kBlock) A.state[e] = SIM_UNK;
+          __syncthreads();
+          batch_group<MODE_CORES>(B, k, eb, ee, T, pc);
+          batch_count(sh_stats, MODE_CORES, k, pc);
+        } else if (ph == BP_HOOK) {
+          for (int64_t e = eb + tid; e < ee; e += kBlock) {
+            if (A.state[e] != SIM_YES) continue;
+            const int2 uv = A.edges[e];
+            if (ld_u8(A.role + uv.x) == ROLE_CORE && ld_u8(A.role + uv.y) == ROLE_CORE) uf_union(A.parent, uv.x, uv.y);
+          }
+        } else if (ph == BP_MERGE) {
+          batch_group<MODE_MERGE>(B, k, eb, ee, T, pc);
+          batch_count(sh_stats, MODE_MERGE, k, pc);
+        } else if (ph == BP_ATTACH) {
+          batch_group<MODE_ATTACH>(B, k, eb, ee, T, pc);
+          batch_count(sh_stats, MODE_ATTACH, k, pc);
+        } else {  // BP_HUBOUT
+          for (int64_t e = eb + tid; e < ee; e += kBlock) {
+            const int2 uv = A.edges[e];
+            const int32_t lu = A.label[uv.x], lv = A.label[uv.y];
+            if ((lu == INT_MAX) == (lv == INT_MAX)) continue;
+            const int32_t x = (lu == INT_MAX) ? uv.x : uv.y;
+            const int32_t L = (lu == INT_MAX) ? lv : lu;
+            const int32_t seen = ld_i32(A.upper + x);
+            if (seen == L) continue;
+            const int32_t old = (seen == -1) ? atomicCAS(A.upper + x, -1, L) : seen;
+            if (old != -1 && old != L) st_u8(A.role + x, ROLE_HUB);
+          }
         }
       }
     }

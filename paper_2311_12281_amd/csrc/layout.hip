@@ -206,8 +206,56 @@ hipError_t exclusive_scan(hipStream_t s, const int64_t* in, int64_t* out, int64_
 
 }  // namespace
 
+int64_t hub_windows(const int32_t* row, int64_t dv, std::vector<uint32_t>& out) {
+  // The same windows the LDS-hash kernel would find: a bitmap of the ids
+  // row[w0] .. row[w0] + kHubBitmapBits - 1 where that range holds at least
+  // kHubBitmapMin elements from w0 on, else a hash set of the next kHubWindow
+  // elements, cut where the longest suffix that one bitmap covers begins (if
+  // that suffix holds at least kHubBitmapMin elements).
+  int64_t wsuf = dv;
+  if (dv >= kHubBitmapMin) {
+    const int64_t T = (int64_t)row[dv - 1] - kHubBitmapBits + 1;
+    const int64_t ws = std::lower_bound(row, row + dv, T, [](int32_t a, int64_t b) { return (int64_t)a < b; }) - row;
+    if (dv - ws >= kHubBitmapMin) wsuf = ws;
+  }
+  int64_t cnt = 0;
+  for (int64_t w0 = 0, w1 = 0; w0 < dv; w0 = w1, ++cnt) {
+    w1 = (dv - w0 > kHubWindow) ? w0 + kHubWindow : dv;
+    if (w0 < wsuf && w1 > wsuf) w1 = wsuf;
+    bool bitmap = false;
+    if (dv - w0 >= kHubBitmapMin) {
+      const int64_t lim = (int64_t)row[w0] + kHubBitmapBits;
+      const int64_t wb = std::lower_bound(row + w0 + 1, row + dv, lim,
+                                          [](int32_t a, int64_t b) { return (int64_t)a < b; }) - row;
+      if (wb - w0 >= kHubBitmapMin) {
+        bitmap = true;
+        w1 = wb;
+      }
+    }
+    out.push_back(((uint32_t)w1 << 1) | (bitmap ? 1u : 0u));
+  }
+  return cnt;
+}
+
+void assign_hub_windows(std::vector<HubJob>& jobs, const int64_t* rp, const int32_t* rows,
+                        std::vector<uint32_t>& table) {
+  table.clear();
+  std::vector<std::pair<int32_t, size_t>> order(jobs.size());
+  for (size_t k = 0; k < jobs.size(); ++k) order[k] = {jobs[k].v, k};
+  std::sort(order.begin(), order.end());
+  for (size_t k = 0; k < order.size();) {
+    const int32_t v = order[k].first;
+    const int32_t wbeg = (int32_t)table.size();
+    const int32_t wcnt = (int32_t)hub_windows(rows + rp[v], rp[v + 1] - rp[v], table);
+    for (; k < order.size() && order[k].first == v; ++k) {
+      jobs[order[k].second].wbeg = wbeg;
+      jobs[order[k].second].wcnt = wcnt;
+    }
+  }
+}
+
 hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
-                             const int32_t* h_ci, int32_t* d_hci) {
+                             const int32_t* h_ci, int32_t* d_hci, std::vector<int32_t>* h_hci) {
   if (nnz <= 0 || n <= 0) return hipSuccess;
   // rank: counting sort of the vertices by increasing degree, ties by id
   int64_t maxd = 0;
@@ -242,17 +290,16 @@ hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_
     });
   for (auto& x : th) x.join();
   hipError_t e = hipMemcpyAsync(d_hci, out.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (h_hci) h_hci->swap(out);
+  return e;
 }
 
 hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
                         const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
-                        int2** d_edges_out, HubJob** d_jobs_out, LayoutResult* out) {
+                        int2** d_edges_out, std::vector<HubJob>* jobs_out, LayoutResult* out) {
   hipError_t e = hipSuccess;
-  int64_t* d_hub = nullptr;
-  HubJob* d_jobs = nullptr;
-  *d_jobs_out = nullptr;
+  jobs_out->clear();
   out->hub_jobs = 0;
   int32_t* d_flags = nullptr;  // [0] = error bits, [1] = max degree
   int32_t* d_src = nullptr;
@@ -351,7 +398,7 @@ hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_
         th.emplace_back([&, t]() {
           for (int32_t v = t; v < n; v += nth) {
             if (cnt[(size_t)v] == 0) continue;
-            HubJob J;
+            HubJob J{};
             J.v = v;
             J.begin = b6 + start[(size_t)v];
             J.count = 0;
@@ -372,26 +419,19 @@ hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_
           }
         });
       for (auto& x : th) x.join();
-      std::vector<HubJob> jobs;
+      std::vector<HubJob>& jobs = *jobs_out;
       for (auto& p : part) jobs.insert(jobs.end(), p.begin(), p.end());
       std::stable_sort(jobs.begin(), jobs.end(), [&](const HubJob& a, const HubJob& b) {
         const int64_t da = deg(a.v), db = deg(b.v);
         return da != db ? da > db : a.begin < b.begin;
       });
       out->hub_jobs = (int64_t)jobs.size();
-      LTRY(hipMalloc((void**)&d_jobs, sizeof(HubJob) * (jobs.empty() ? 1 : jobs.size())));
-      LTRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice, s));
-      LTRY(hipStreamSynchronize(s));
     }
   }
   *d_edges_out = d_edges;
   d_edges = nullptr;
-  *d_jobs_out = d_jobs;
-  d_jobs = nullptr;
 done:
   hipStreamSynchronize(s);
-  if (d_hub) hipFree(d_hub);
-  if (d_jobs) hipFree(d_jobs);
   if (d_edges) hipFree(d_edges);
   if (d_cnt) hipFree(d_cnt);
   if (d_src) hipFree(d_src);

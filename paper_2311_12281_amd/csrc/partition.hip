@@ -53,8 +53,8 @@ void part_release(scan_graph* g) {
   if (P.h_edges) (void)hipHostFree(P.h_edges);
   if (P.h_state) (void)hipHostFree(P.h_state);
   if (P.h_ecount) (void)hipHostFree(P.h_ecount);
-  void* d[] = {P.d_rows, P.d_edges, P.d_state, P.d_edges2, P.d_state2, P.d_ecount, P.d_jobs, P.d_worklist,
-               P.d_jobctr};
+  void* d[] = {P.d_rows, P.d_edges, P.d_state, P.d_edges2, P.d_state2, P.d_ecount, P.d_jobs, P.d_wtab,
+               P.d_worklist, P.d_jobctr};
   for (void* p : d)
     if (p) (void)hipFree(p);
   for (int b = 0; b < 2; ++b) {
@@ -220,7 +220,7 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
     const int64_t b6 = C.bucket_off[kNumBuckets - 1], e6 = C.bucket_off[kNumBuckets];
     for (int64_t k = b6; k < e6;) {
       const int32_t v = P.h_edges[k].y;
-      HubJob J;
+      HubJob J{};
       J.v = v;
       J.begin = k - C.begin;
       J.count = 0;
@@ -244,11 +244,15 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
       return rp[a.v + 1] - rp[a.v] > rp[b.v + 1] - rp[b.v];
     });
   }
+  // windows of the hub rows (the raw rows: the kernel reads them as given here)
+  std::vector<uint32_t> wtab;
+  assign_hub_windows(jobs, rp, ci, wtab);
   P.row_cap = row_cap;
   P.chunk_cap = chunk_cap;
   // rows are read up to kColPad elements past their end by the LDS-hash kernel
   if ((e = hipMalloc((void**)&P.d_rows, sizeof(int32_t) * (size_t)(std::max<int64_t>(row_cap, 1) + kColPad))) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_jobs, sizeof(HubJob) * std::max<size_t>(jobs.size(), 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&P.d_wtab, sizeof(uint32_t) * std::max<size_t>(wtab.size(), 1))) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_worklist, sizeof(int32_t) * (size_t)chunk_cap)) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_jobctr, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc((void**)&P.d_edges, sizeof(int2) * (size_t)chunk_cap)) != hipSuccess ||
@@ -263,7 +267,8 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
       (e = hipEventCreateWithFlags(&P.done[1], hipEventDisableTiming)) != hipSuccess)
     return fail_hip(e, "device buffers");
   if (!jobs.empty() &&
-      (e = hipMemcpy(P.d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      ((e = hipMemcpy(P.d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+       (e = hipMemcpy(P.d_wtab, wtab.data(), sizeof(uint32_t) * wtab.size(), hipMemcpyHostToDevice)) != hipSuccess))
     return fail_hip(e, "job table");
   g->partitioned = true;
   g->m = m;
@@ -379,6 +384,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
   EdgeArgs A{};
   A.rp = g->d_rp;
   A.edges = P.d_edges;
+  A.wtab = P.d_wtab;
   A.state = P.d_state;
   A.lower = g->d_lower;
   A.upper = g->d_upper;
@@ -502,6 +508,7 @@ int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
   EdgeArgs A{};
   A.rp = g->d_rp;
   A.edges = P.d_edges;
+  A.wtab = P.d_wtab;
   A.edge_counts = P.d_ecount;
   A.stats = g->d_stats;
   A.p = 1;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace scan {
 
 // Per-vertex role during the run (Table 1 of the paper: ?, C, !C).
@@ -90,13 +92,24 @@ struct HubJob {
   int64_t begin;  // first edge of the job
   int32_t v;      // common larger side
   int32_t count;  // edges in the job (<= kHubJobEdges)
+  int32_t wbeg;   // v's windows: entries wbeg .. wbeg + wcnt - 1 of the window table
+  int32_t wcnt;   // (0: none computed, the kernel finds them)
 };
+// Window table entry: (end of the window in v's row) << 1 | (1 if a bitmap window).
+// The windows of a row depend only on the row, so they are computed once per
+// hub vertex when the graph is created (hub_windows) rather than by the kernel.
+int64_t hub_windows(const int32_t* row, int64_t dv, std::vector<uint32_t>& out);
+// Fills wbeg / wcnt of every job from the rows the kernel reads (row of v at
+// rows + rp[v]) and returns the window table.
+void assign_hub_windows(std::vector<HubJob>& jobs, const int64_t* rp, const int32_t* rows,
+                        std::vector<uint32_t>& table);
 
 struct EdgeArgs {
   const int64_t* rp;
   const int32_t* ci;
   const int32_t* hci;  // rows read by the LDS-hash kernel: ci, or ci renamed by degree rank
   const int2* edges;  // oriented: x = smaller side (deg, id), y = larger side
+  const uint32_t* wtab;  // LDS-hash windows of the jobs' larger sides (HubJob::wbeg)
   int64_t e_begin, e_end;
   uint8_t* state;     // per oriented edge
   int32_t* lower;     // confirmed |N_eps| lower bound (starts at 1)
@@ -195,13 +208,15 @@ __host__ __device__ inline bool batch_vertex_phase(int ph) {
   return ph == BP_INIT || ph == BP_FINAL || ph == BP_FLAT || ph == BP_OUTPUT;
 }
 // Tiles of phase ph for a graph of n vertices with ek[k] edges in bucket k.
+// An edge tile is tile_edges consecutive edges of the graph's bucket ranges
+// taken one after the other (so a tile may span several buckets).
 __host__ __device__ inline int64_t batch_phase_tiles(int ph, int64_t n, const int64_t* ek, int64_t tile_edges,
                                                      int64_t tile_vertices, int split) {
   if (ph == BP_HUBOUT && !split) return 0;
   if (batch_vertex_phase(ph)) return (n + tile_vertices - 1) / tile_vertices;
-  int64_t t = 0;
-  for (int k = 0; k < kNumBuckets; ++k) t += (ek[k] + tile_edges - 1) / tile_edges;
-  return t;
+  int64_t m = 0;
+  for (int k = 0; k < kNumBuckets; ++k) m += ek[k];
+  return (m + tile_edges - 1) / tile_edges;
 }
 
 struct BatchArgs {
@@ -209,7 +224,8 @@ struct BatchArgs {
   int32_t G;
   const int64_t* vtx_off;        // [G + 1] first vertex of each graph in the union
   const int64_t* eoff;           // [kNumBuckets * (G + 1)]: first edge of graph g in bucket k
-  int32_t lanes[kNumBuckets];    // lane-group width per bucket (4, 8, 16, 32 or 64)
+  uint32_t lanes_code;           // lane-group width of bucket k: 4 << ((lanes_code >> 3k) & 7)
+                                 // (a scalar, so that no kernel argument is indexed at run time)
   int32_t tile_edges;            // edges per edge tile (a multiple of 64)
   int32_t tile_vertices;         // vertices per vertex tile
   int32_t split;                 // hub / outlier roles
@@ -245,18 +261,20 @@ struct LayoutResult {
 // Validates the CSR and builds the oriented, bucketed edge list and the job
 // table of the last bucket, both allocated here (caller frees):
 //   *d_edges: bucket_off[kNumBuckets] entries, *d_jobs: hub_jobs entries.
+// The job table is returned on the host (jobs), to be completed with the
+// windows and uploaded by the caller.
 hipError_t build_layout(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
                         const int32_t* h_ci, const int64_t* d_rp, const int32_t* d_ci, int validate,
-                        int2** d_edges, HubJob** d_jobs, LayoutResult* out);
+                        int2** d_edges, std::vector<HubJob>* jobs, LayoutResult* out);
 // Fills d_hci (nnz entries) with the rows of the CSR with every vertex renamed
 // to its rank in order of increasing degree (ties by id), each row sorted
-// again.  Intersection sizes do not depend on the names.  The top
+// again (also returned in h_hci).  Intersection sizes do not depend on the names.  The top
 // kHubBitmapBits ranks hold most arc endpoints of a skewed graph, so the
 // LDS-hash kernel covers most of a long row with one bitmap window, and a
 // survivor's low-degree neighbours, the likely misses, come first, which
 // settles dissimilar edges earlier.  Built on the host threads and copied;
 // synchronous.
 hipError_t build_ranked_rows(hipStream_t s, int32_t n, int64_t nnz, const int64_t* h_rp,
-                             const int32_t* h_ci, int32_t* d_hci);
+                             const int32_t* h_ci, int32_t* d_hci, std::vector<int32_t>* h_hci);
 
 }  // namespace scan
