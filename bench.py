@@ -416,16 +416,12 @@ def bench_serving(args):
     log(f"{len(graphs)} resident + {len(uploads)} upload R-MAT graphs, {sum(g.m for g in graphs)} + "
         f"{sum(g.m for g in uploads)} edges, generated in {time.perf_counter() - t:.0f}s")
     nslots = args.serve_slots
-    served_bytes = lambda g: S.scan_graph_footprint(g.n, g.nnz, S.make_opts()) + 12 * g.m  # noqa: E731
-    slot_bytes = nslots * max(18 * g.n + g.m for g in graphs + uploads)
-    # budget: every resident graph and all uploads but the last fit (its queries use the fallback)
-    budget = sum(served_bytes(g) for g in graphs + uploads[:-1]) + slot_bytes + (64 << 20)
-    srv = S.Server(num_slots=nslots, budget=budget)
+    srv = S.Server(num_slots=nslots)
     t = time.perf_counter()
     gids = [srv.add(g) for g in graphs]
     add_s = time.perf_counter() - t
-    log(f"added {len(gids)} graphs in {add_s:.1f}s; budget {budget / 2**30:.1f} GiB, held "
-        f"{srv.info()['resident_bytes'] / 2**30:.1f} GiB")
+    log(f"added {len(gids)} graphs in {add_s:.1f}s; held {srv.info()['resident_bytes'] / 2**30:.1f} GiB")
+    budget = None
     all_graphs = graphs + uploads
     rng = np.random.default_rng(7)
     nq = args.serve_queries
@@ -467,10 +463,15 @@ def bench_serving(args):
                 dig[k] = result_digest(lab, rol)
 
         def uploader():
+            nonlocal budget
             for j, g in enumerate(uploads):
                 d = start + (j + 1) * args.serve_upload_every - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
+                if j == len(uploads) - 1:
+                    # admission limit: what is held now; the last upload stays on the host
+                    budget = srv.info()["resident_bytes"] + (32 << 20)
+                    srv.set_budget(budget)
                 gid = srv.add(g)
                 g_index[gid] = len(graphs) + j
                 upload_gids.append(gid)

@@ -240,6 +240,11 @@ int scan_server_create(const scan_opts* opts, int32_t num_slots, scan_server** o
 int scan_server_add_graph(scan_server* s, int32_t n, int64_t nnz, const int64_t* row_ptr,
                           const int32_t* col_idx, int32_t* gid_out);
 
+/* Replaces the admission limit (0 = no cap) for graphs added from now on and
+ * for the partition-based graphs of later fallback queries; graphs already
+ * resident stay resident. */
+int scan_server_set_budget(scan_server* s, uint64_t device_budget_bytes);
+
 /* Waits for the graph's queued and running queries, then releases it. */
 int scan_server_remove_graph(scan_server* s, int32_t gid);
 

@@ -33,6 +33,7 @@ EXPORTED = [
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
     "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint", "scan_batch_set_params",
+    "scan_server_set_budget",
 ]
 
 
@@ -125,6 +126,7 @@ def lib():
         L.scan_server_create.argtypes = [P(scan_opts), i32, P(vp)]
         L.scan_server_add_graph.argtypes = [vp, i32, i64, vp, vp, P(i32)]
         L.scan_server_remove_graph.argtypes = [vp, i32]
+        L.scan_server_set_budget.argtypes = [vp, u64]
         L.scan_server_submit.argtypes = [vp, i32, i64, i64, i32, P(i64)]
         L.scan_server_wait.argtypes = [vp, i64, vp, vp, P(ctypes.c_double)]
         L.scan_server_info.argtypes = [vp, P(u64), P(i32), P(i32), P(i64)]
@@ -145,7 +147,7 @@ def lib():
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
                      "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc",
-                     "scan_graph_footprint", "scan_batch_set_params"):
+                     "scan_graph_footprint", "scan_batch_set_params", "scan_server_set_budget"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -423,6 +425,9 @@ class Server:
     def remove(self, gid: int) -> None:
         scan_server_remove_graph(self.handle, gid)
         self.sizes.pop(gid, None)
+
+    def set_budget(self, nbytes: int) -> None:
+        _check(lib().scan_server_set_budget(self.handle, int(nbytes)))
 
     def submit(self, gid: int, p: int, q: int, mu: int) -> int:
         return scan_server_submit(self.handle, gid, p, q, mu)

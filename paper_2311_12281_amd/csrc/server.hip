@@ -482,6 +482,13 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
   return SCAN_OK;
 }
 
+int scan_server_set_budget(scan_server* S, uint64_t device_budget_bytes) {
+  if (!S) return fail(SCAN_E_INVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->budget = device_budget_bytes;
+  return SCAN_OK;
+}
+
 int scan_server_remove_graph(scan_server* S, int32_t gid) {
   if (!S) return fail(SCAN_E_INVAL, "server is NULL");
   std::unique_lock<std::mutex> lk(S->mu);

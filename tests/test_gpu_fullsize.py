@@ -11,6 +11,11 @@ compares the GPU library's results digest for digest.
   U[8, 64], 5-200 blocks, per-graph eps in {1/5, 2/5, 3/5, 4/5} and mu in
   2..10, seed 4; about 677 M edges in all) clustered in one persistent batched
   run: every graph's labels and roles.
+- Serving: 64 resident R-MAT graphs (scale 16..23, edge factor 8..32) and 8
+  more added while queries run, under a device budget that keeps the last one
+  on the host (its queries take the partition-based path): two stored oracle
+  results per graph, and every query of a concurrent stream equal to the same
+  query run alone.
 """
 import json
 import os
@@ -82,3 +87,71 @@ def test_planted_batch_10000_matches_oracle():
             bad = [k for k, (l, r) in enumerate(zip(B.split(labels), B.split(roles)))
                    if result_digest(l, r)[:12] != gold["result_sha256_12"][k]]
             assert not bad, f"{len(bad)} graphs differ from the oracle, first {bad[:10]}"
+
+
+def test_serving_64_graphs_with_uploads_match_oracle():
+    import threading
+
+    gold = _golden("serving_rmat72_seed5.json")
+    res_specs, up_specs = gg.serving_specs(count=gold["count"], uploads=gold["uploads"], seed=gold["seed"])
+    t = time.perf_counter()
+    graphs = [sp.make() for sp in res_specs + up_specs]
+    note("serving graphs generated", len(graphs), f"{time.perf_counter() - t:.0f}s")
+    for k, (g, gr) in enumerate(zip(graphs, gold["graphs"])):
+        assert g.m == gr["m"] and csr_digest(g) == gr["csr_sha256"], f"graph {k} differs from the oracle's input"
+    resident, uploads = graphs[:gold["count"]], graphs[gold["count"]:]
+    nslots = 4
+    rng = np.random.default_rng(11)
+    with S.Server(num_slots=nslots) as srv:
+        t = time.perf_counter()
+        gids = [srv.add(g) for g in resident]
+        note("resident graphs added", f"{time.perf_counter() - t:.0f}s", srv.info())
+        stream = []  # (gid, p, q, mu, labels digest) of every query of the concurrent stream
+        lock = threading.Lock()
+        up_gids = []
+
+        def uploader():
+            for j, g in enumerate(uploads):
+                if j == len(uploads) - 1:
+                    # the admission limit drops to what is held now: the last upload stays on the host
+                    srv.set_budget(srv.info()["resident_bytes"] + (32 << 20))
+                gid = srv.add(g)
+                with lock:
+                    up_gids.append(gid)
+
+        th = threading.Thread(target=uploader)
+        th.start()
+        pending = []
+        while th.is_alive() or len(pending) < 600:
+            with lock:
+                pool = gids + up_gids[:-1] if len(up_gids) == len(uploads) else gids + up_gids
+            gid = pool[int(rng.integers(len(pool)))]
+            p, mu = int(rng.integers(1, 10)), int(rng.integers(2, 21))
+            pending.append((srv.submit(gid, p, 10, mu), gid, p, mu))
+            if len(pending) % 50 == 0:
+                for r, gid_, p_, mu_ in pending[-50:]:
+                    lab, rol, _ = srv.wait(r, gid_)
+                    stream.append((gid_, p_, mu_, result_digest(lab, rol)))
+            if len(pending) > 3000:
+                break
+        th.join()
+        for r, gid_, p_, mu_ in pending[len(stream):]:
+            lab, rol, _ = srv.wait(r, gid_)
+            stream.append((gid_, p_, mu_, result_digest(lab, rol)))
+        info = srv.info()
+        note("stream done", len(stream), info)
+        assert info["graphs"] == len(graphs) and info["resident_graphs"] == len(graphs) - 1
+        all_gids = gids + up_gids
+        for k, gr in enumerate(gold["graphs"]):
+            for run in gr["runs"]:
+                (p, q), mu = run["eps"], run["mu"]
+                lab, rol, _ = srv.wait(srv.submit(all_gids[k], p, q, mu), all_gids[k])
+                assert result_digest(lab, rol) == run["result_sha256"], f"graph {k} eps={p}/{q} mu={mu}"
+        note("oracle digests matched", sum(len(gr["runs"]) for gr in gold["graphs"]))
+        alone = {}
+        for gid, p, mu, d in stream:
+            if (gid, p, mu) not in alone:
+                lab, rol, _ = srv.wait(srv.submit(gid, p, 10, mu), gid)
+                alone[(gid, p, mu)] = result_digest(lab, rol)
+            assert alone[(gid, p, mu)] == d, f"graph {gid} eps={p}/10 mu={mu}: differs from its alone-run"
+        note("alone-runs matched", len(stream), "queries,", len(alone), "distinct")
