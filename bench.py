@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched"])
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched", "sweep"])
     ap.add_argument("--cl-n", type=int, default=50_000_000, help="partitioned: Chung-Lu vertices")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="partitioned: device budget")
     ap.add_argument("--serve-graphs", type=int, default=64, help="serving: resident R-MAT graphs")
@@ -90,6 +90,8 @@ def main():
         return bench_serving(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import graphgen as gg
     import paper_2311_12281_amd as S
@@ -165,6 +167,33 @@ def main():
     log(f"streaming copy {args.copy_mib} MiB: {copy_ms:.3f} ms -> {copy_gbps:.0f} GB/s")
     dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
     traffic = _traffic_from_profile(dom_kernel)
+    # every bucket's kernel against the same roofline, and the whole cores pass
+    buckets = []
+    for b in range(nb):
+        ms_l = ms_b[b] / launches
+        alg_l = bytes_b[b] / launches
+        buckets.append({"bucket": b, "launch_ms": float(ms_l), "alg_bytes_per_launch": float(alg_l),
+                        "achieved_GBs": float(alg_l / (ms_l * 1e-3) / 1e9) if ms_l > 0 else 0.0,
+                        "frac": float(alg_l / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS) if ms_l > 0 else 0.0,
+                        "edges": int(stats[0]["bucket_edges"][b])})
+    cores_ms = sum(st["ms_phase"]["cores"] for st in stats) / launches
+    cores_alg = float(bytes_b.sum() / launches)
+    cores_pass = {"launch_ms": cores_ms, "alg_bytes_per_launch": cores_alg,
+                  "frac": cores_alg / (cores_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if cores_ms > 0 else 0.0}
+    # the non-degenerate point of this graph (eps = 1/10 has cores and clusters), timed beside the step
+    dl10, dr10 = S.scan_device_alloc(4 * n), S.scan_device_alloc(n)
+    for _ in range(2):
+        G.run_device(1, 10, MU, dl10, dr10)
+    t10 = []
+    st10 = None
+    for _ in range(max(3, args.steps // 2)):
+        t = time.perf_counter()
+        G.run_device(1, 10, MU, dl10, dr10)
+        t10.append(time.perf_counter() - t)
+        st10 = G.stats()
+    eps10 = {"eps": "1/10", "ms_wall": float(np.median(t10) * 1e3), "ms_device": st10["ms_total"],
+             "ms_phase": st10["ms_phase"], "edges_per_s": float(m / np.median(t10))}
+    log(f"eps=1/10 (not in the headline step): {eps10['ms_wall']:.1f} ms, {eps10['edges_per_s'] / 1e9:.2f} G edges/s")
 
     # PCIe-inclusive rate (host outputs), reported beside the value
     t = time.perf_counter()
@@ -187,8 +216,20 @@ def main():
         cpu_s = time.perf_counter() - t
         cpu = {"value": m / cpu_s, "unit": "edges/s", "cores": threads, "kind": "oracle",
                "sample": f"full R-MAT scale {args.scale} graph (m={m}) at eps=1/2 mu={MU}: "
-                         f"closed counts of every edge + clustering, {cpu_s:.1f} s"}
+                         f"closed counts of every edge + clustering, {cpu_s:.1f} s",
+               "cpu_model": _cpu_model()}
         log(f"oracle: {cpu_s:.1f} s -> {m / cpu_s / 1e6:.2f} M edges/s")
+        if not args.no_cpu_baseline:
+            # one thread, on a bounded sample: R-MAT scale 20 from the same generator
+            g1 = gg.rmat(args.scale - 2, args.edge_factor, seed=args.seed)
+            t = time.perf_counter()
+            oracle.scan(g1, 1, 2, MU, threads=1)
+            t1 = time.perf_counter() - t
+            cpu["t1"] = {"value": g1.m / t1, "unit": "edges/s", "cores": 1,
+                         "sample": f"R-MAT scale {args.scale - 2} ef {args.edge_factor} (m={g1.m}) at eps=1/2 "
+                                   f"mu={MU}, one thread: {t1:.1f} s"}
+            log(f"oracle, one thread, R-MAT scale {args.scale - 2}: {t1:.1f} s -> {g1.m / t1 / 1e6:.2f} M edges/s")
+            del g1
         if not args.no_verify:
             exact = True
             for k, (p, q) in enumerate(EPS_SET):
@@ -241,8 +282,28 @@ def main():
         "scan_similarity_device_ms": sim_stats["ms_total"],
         "graph_create_ms": create_s * 1e3,
         "per_eps": per_eps,
+        "eps_1_10": eps10,
+        "cores_pass": cores_pass,
+        "buckets": buckets,
     }
+    S.scan_device_free(dl10)
+    S.scan_device_free(dr10)
     print(json.dumps(line), flush=True)
+
+
+def _cpu_model():
+    """CPU model name and logical CPU count of this host (lscpu)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:
+        return None
+    info = {}
+    for ln in out.splitlines():
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            info[k.strip()] = v.strip()
+    return {"model": info.get("Model name"), "cpus": info.get("CPU(s)"), "nproc": os.cpu_count()}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_hub_cores_rmat22.md")
@@ -401,13 +462,22 @@ def bench_serving(args):
     at the same arrivals.  Latency = completion - arrival.  Exactness: the
     stored oracle digests of two queries per graph, and every query of the
     Poisson runs against the same query run alone afterwards."""
-    import hashlib
     import threading
+
+    import xxhash
 
     import graphgen as gg
     import paper_2311_12281_amd as S
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     from digest import result_digest
+
+    def fast_digest(labels, roles):
+        # compares the stream's results with their alone-runs (the oracle
+        # digests use result_digest); quick enough for the waiting thread
+        h = xxhash.xxh3_128()
+        h.update(np.ascontiguousarray(labels))
+        h.update(np.ascontiguousarray(roles))
+        return h.hexdigest()
 
     res_specs, up_specs = gg.serving_specs(count=args.serve_graphs, uploads=args.serve_uploads, seed=5)
     t = time.perf_counter()
@@ -460,7 +530,7 @@ def bench_serving(args):
                 r, gid = keys[k][0], keys[k][1]
                 lab, rol, ms = srv.wait(r, gid)
                 lat[k] = ms
-                dig[k] = result_digest(lab, rol)
+                dig[k] = fast_digest(lab, rol)
 
         def uploader():
             nonlocal budget
@@ -574,7 +644,7 @@ def bench_serving(args):
         key = (gid, p, q, mu)
         if key not in alone:
             lab, rol, _ = srv.wait(srv.submit(gid, p, q, mu), gid)
-            alone[key] = result_digest(lab, rol)
+            alone[key] = fast_digest(lab, rol)
         alone_ok = alone_ok and alone[key] == d
     log(f"every query equals its alone-run: {alone_ok} ({len(checks)} queries, {len(alone)} distinct)")
     srv.close()
@@ -588,10 +658,15 @@ def bench_serving(args):
 def bench_batched(args):
     """Many planted-partition graphs (n log-uniform in [100, 20000], mean
     degree U[8, 64], 5-200 blocks, per-graph eps in {1/5..4/5}, mu in 2..10):
-    one captured launch for the batch vs one scan_run per graph."""
+    one persistent batched launch (autotuned, captured in a HIP graph) vs the
+    plain path, one scan_run per graph.  Every graph's result is compared with
+    the stored oracle digests (10,000 graphs, seed 4) or, for other counts,
+    with the oracle on a sample."""
     import graphgen as gg
     import oracle
     import paper_2311_12281_amd as S
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from digest import result_digest
 
     t = time.perf_counter()
     graphs, specs = gg.planted_batch(args.batch_count, seed=4)
@@ -604,32 +679,99 @@ def bench_batched(args):
     B = S.Batch(graphs, eps, mus, autotune=True)
     create_s = time.perf_counter() - t
     lanes, tile = B.config()
-    B.run()
+    log(f"batch created and autotuned in {create_s:.1f}s: lanes {lanes}, {tile} edges per tile")
+    for _ in range(args.warmup):
+        B.run(replay=True)
+    dev_ms = []
     t = time.perf_counter()
     for _ in range(args.steps):
         labels, roles = B.run(replay=True)
-    batch_s = (time.perf_counter() - t) / args.steps
-    # plain: one resident graph per input, one scan_run each
-    plain = [S.Graph.from_csr(g) for g in graphs]
-    t = time.perf_counter()
-    res = [G.run(p, q, mu) for G, (p, q), mu in zip(plain, eps, mus)]
-    plain_s = time.perf_counter() - t
-    for G in plain:
-        G.close()
+        dev_ms.append(B.stats()["ms_total"])
+    wall_s = (time.perf_counter() - t) / args.steps
+    batch_ms = float(np.median(dev_ms))
+    log(f"batched: {batch_ms:.1f} ms device per run ({m / batch_ms / 1e6:.2f} G edges/s), "
+        f"{wall_s * 1e3:.1f} ms wall with host outputs")
     ls, rs = B.split(labels), B.split(roles)
-    same = all(np.array_equal(a[0], b) and np.array_equal(a[1], c) for a, b, c in zip(res, ls, rs))
-    rng = np.random.default_rng(0)
-    sample = rng.choice(len(graphs), size=min(200, len(graphs)), replace=False)
-    oracle_ok = True
-    for k in sample:
-        ol, orr = oracle.scan(graphs[k], *eps[k], mus[k])
-        oracle_ok = oracle_ok and bool(np.array_equal(ol, ls[k]) and np.array_equal(orr, rs[k]))
+    gold_path = os.path.join(ROOT, "tests", "golden", "planted_batch_10000_seed4.json")
+    if args.batch_count == 10000 and os.path.exists(gold_path):
+        with open(gold_path) as fh:
+            gold = json.load(fh)["result_sha256_12"]
+        bad = sum(result_digest(l, r)[:12] != gd for l, r, gd in zip(ls, rs, gold))
+        exact = {"checked": "every graph against the oracle digests", "graphs_differing": bad}
+    else:
+        rng = np.random.default_rng(0)
+        sample = rng.choice(len(graphs), size=min(200, len(graphs)), replace=False)
+        bad = 0
+        for k in sample:
+            ol, orr = oracle.scan(graphs[k], *eps[k], mus[k])
+            bad += not (np.array_equal(ol, ls[k]) and np.array_equal(orr, rs[k]))
+        exact = {"checked": f"{len(sample)} sampled graphs against the oracle", "graphs_differing": bad}
+    log(f"exactness: {exact}")
+    # plain: one graph at a time (created, one timed scan_run, destroyed), the same results
+    plain_s = 0.0
+    same = True
+    for k, g in enumerate(graphs):
+        with S.Graph.from_csr(g) as G:
+            t = time.perf_counter()
+            gl, gr = G.run(*eps[k], mus[k])
+            plain_s += time.perf_counter() - t
+        same = same and bool(np.array_equal(gl, ls[k]) and np.array_equal(gr, rs[k]))
+    log(f"plain: {plain_s * 1e3:.0f} ms for {len(graphs)} scan_run calls ({m / plain_s / 1e9:.3f} G edges/s); "
+        f"identical to batched: {same}")
     B.close()
-    _line("edges/s (|E|/solve) exact-match, batched", m / batch_s, "edges/s",
+    _line("edges/s (|E|/solve) exact-match, batched", m / (batch_ms * 1e-3), "edges/s",
           {"workload": f"planted_batch_{len(graphs)}", "graphs": len(graphs), "m": m},
-          ms_per_batch=batch_s * 1e3, plain_edges_per_s=m / plain_s, plain_ms=plain_s * 1e3,
-          identical_to_plain=same, oracle_sample_exact=oracle_ok, autotuned_lanes=lanes, tile_edges=tile,
-          create_s=create_s)
+          ms_per_batch_device=batch_ms, ms_per_batch_wall=wall_s * 1e3, plain_edges_per_s=m / plain_s,
+          plain_ms=plain_s * 1e3, identical_to_plain=same, exactness=exact, autotuned_lanes=lanes,
+          tile_edges=tile, create_s=create_s)
+
+
+def bench_sweep(args):
+    """R-MAT scale 22: eps in {0.2 .. 0.8} at mu = 6, and mu in {3, 6, 11, 16,
+    31} at eps = 0.5 (the axes of the paper's experiments on eps and mu), with
+    the device time of every phase; every result is compared with the oracle
+    (closed counts once, then the clustering of each point)."""
+    import graphgen as gg
+    import oracle
+    import paper_2311_12281_amd as S
+
+    g = gg.rmat(args.scale, args.edge_factor, seed=args.seed)
+    n, m = g.n, g.m
+    G = S.Graph.from_csr(g, timing=True)
+    dl, dr = S.scan_device_alloc(4 * n), S.scan_device_alloc(n)
+    oc = oracle.counts(g, threads=oracle.max_threads())
+    points = [((k, 10), 6) for k in range(2, 9)] + [((1, 2), mu) for mu in (3, 6, 11, 16, 31)]
+    rows = []
+    for (p, q), mu in points:
+        G.run_device(p, q, mu, dl, dr)  # warm-up
+        walls, sts = [], []
+        for _ in range(max(3, args.steps // 2)):
+            t = time.perf_counter()
+            G.run_device(p, q, mu, dl, dr)
+            walls.append(time.perf_counter() - t)
+            sts.append(G.stats())
+        gl = np.empty(n, np.int32)
+        gr = np.empty(n, np.uint8)
+        S.scan_memcpy_d2h(gl, dl, 4 * n)
+        S.scan_memcpy_d2h(gr, dr, n)
+        ol, orr = oracle.cluster(g, oc, p, q, mu)
+        exact = bool(np.array_equal(gl, ol) and np.array_equal(gr, orr))
+        wall = float(np.median(walls))
+        row = {"eps": f"{p}/{q}", "mu": mu, "ms_wall": wall * 1e3, "edges_per_s": m / wall,
+               "ms_phase": {ph: float(np.median([st["ms_phase"][ph] for st in sts])) for ph in S.PHASES},
+               "ms_cores_bucket": [float(np.median([st["ms_cores_bucket"][b] for st in sts])) for b in range(7)],
+               "evaluated_cores": int(sts[-1]["evaluated"]["cores"]), "evaluated_merge": int(sts[-1]["evaluated"]["merge"]),
+               "cores": int((orr == 1).sum()), "clusters": int(np.unique(ol[orr == 1]).size),
+               "exact_match": exact}
+        rows.append(row)
+        log(f"eps={p}/{q} mu={mu}: {row['ms_wall']:.1f} ms, cores {row['cores']}, exact {exact}, "
+            f"phases {{{', '.join(f'{k}: {v:.2f}' for k, v in row['ms_phase'].items())}}}")
+    S.scan_device_free(dl)
+    S.scan_device_free(dr)
+    G.close()
+    _line("edges/s (|E|/solve) exact-match, eps and mu sweep", float(np.median([r["edges_per_s"] for r in rows])),
+          "edges/s", {"workload": f"rmat{args.scale}_ef{args.edge_factor}_sweep", "n": n, "m": m},
+          exact_match=all(r["exact_match"] for r in rows), points=rows)
 
 
 if __name__ == "__main__":

@@ -3,10 +3,13 @@
 // (no intersection), which needs only streaming passes over the edges.
 //
 // Continuous batching: a dispatcher thread admits queued requests onto free
-// slots as soon as slots free up; each slot owns a HIP stream, per-query
-// scratch and pinned output buffers, so requests that arrive while others are
-// running overlap on the device.  Completion is detected with events, results
-// are copied out of the slot's pinned buffers and the slot is reused.
+// slots as soon as slots free up; each slot owns a HIP stream and per-query
+// scratch, so requests that arrive while others are running overlap on the
+// device.  A query's result goes to a pinned host buffer taken from a pool;
+// on completion (detected with an event) the buffer is handed to the request
+// and the slot is reused at once, and the waiting caller's thread copies the
+// result out and gives the buffer back.  The pool is bounded: when every
+// buffer holds a result not yet collected, admissions wait for one.
 //
 // Memory admission: a graph is made resident only if its footprint (the
 // in-memory layout as scan_graph_create builds it, degree-ranked rows
@@ -45,6 +48,19 @@ struct ServedGraph {
   bool removing = false;
 };
 
+// Pinned host buffer for one query's labels and roles.
+struct OutBuf {
+  int32_t* labels = nullptr;
+  uint8_t* roles = nullptr;
+  int32_t cap = 0;
+};
+
+void free_out(OutBuf& b) {
+  if (b.labels) (void)hipHostFree(b.labels);
+  if (b.roles) (void)hipHostFree(b.roles);
+  b = OutBuf();
+}
+
 struct Request {
   int64_t id = 0;
   int32_t gid = 0;
@@ -53,8 +69,10 @@ struct Request {
   Clock::time_point t_submit, t_done;
   int status = 1;  // 1 pending/running, 0 ok, < 0 error
   std::string error;
-  std::vector<int32_t> labels;
+  std::vector<int32_t> labels;   // fallback path
   std::vector<uint8_t> roles;
+  OutBuf out;                    // resident path: the result, until collected
+  int32_t n = 0;
 };
 
 struct Slot {
@@ -64,8 +82,7 @@ struct Slot {
   int64_t cap_m = 0;
   int32_t *d_lower = nullptr, *d_parent = nullptr, *d_label = nullptr, *d_out_labels = nullptr;
   uint8_t *d_role = nullptr, *d_state = nullptr, *d_out_roles = nullptr;
-  int32_t* h_labels = nullptr;  // pinned
-  uint8_t* h_roles = nullptr;   // pinned
+  OutBuf out;                    // the running request's result buffer
   std::shared_ptr<Request> req;  // running request, or null
 };
 
@@ -93,12 +110,8 @@ void free_slot_buffers(Slot& s) {
   void* d[] = {s.d_lower, s.d_parent, s.d_label, s.d_out_labels, s.d_role, s.d_state, s.d_out_roles};
   for (void* p : d)
     if (p) (void)hipFree(p);
-  if (s.h_labels) (void)hipHostFree(s.h_labels);
-  if (s.h_roles) (void)hipHostFree(s.h_roles);
   s.d_lower = s.d_parent = s.d_label = s.d_out_labels = nullptr;
   s.d_role = s.d_state = s.d_out_roles = nullptr;
-  s.h_labels = nullptr;
-  s.h_roles = nullptr;
   s.cap_n = 0;
   s.cap_m = 0;
 }
@@ -114,8 +127,6 @@ hipError_t alloc_slot_buffers(Slot& s, int32_t n, int64_t m) {
   if ((e = hipMalloc((void**)&s.d_role, N)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&s.d_out_roles, N)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&s.d_state, M)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&s.h_labels, 4 * N, hipHostMallocDefault)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&s.h_roles, N, hipHostMallocDefault)) != hipSuccess) return e;
   s.cap_n = n;
   s.cap_m = m;
   return hipSuccess;
@@ -148,6 +159,9 @@ struct scan_server {
   FallbackGraph fb;
   std::map<int64_t, std::shared_ptr<Request>> requests;
   std::vector<Slot> slots;
+  std::vector<OutBuf> out_free;  // result buffers not in use
+  int32_t out_total = 0;         // result buffers allocated
+  int32_t out_max = 0;           // bound on them
   int32_t slot_n = 0;  // slot scratch capacity
   int64_t slot_m = 0;
   int64_t completed = 0;
@@ -243,14 +257,19 @@ bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& 
     r->error = "slot scratch smaller than the graph";
     return false;
   }
+  if (!slot.out.labels || slot.out.cap < G->n) {
+    r->status = SCAN_E_NOMEM;
+    r->error = "no result buffer";
+    return false;
+  }
   launch_rethreshold(slot.stream, G->n, G->m, g->d_edges, G->d_ecount, G->d_ab, (uint64_t)p, (uint64_t)q,
                      r->mu, slot.d_lower, slot.d_role, slot.d_parent, slot.d_label, slot.d_state,
                      slot.d_out_labels, slot.d_out_roles, S->opts.hub_outlier ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && G->n > 0)
-    e = hipMemcpyAsync(slot.h_labels, slot.d_out_labels, 4 * (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
+    e = hipMemcpyAsync(slot.out.labels, slot.d_out_labels, 4 * (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
   if (e == hipSuccess && G->n > 0)
-    e = hipMemcpyAsync(slot.h_roles, slot.d_out_roles, (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
+    e = hipMemcpyAsync(slot.out.roles, slot.d_out_roles, (size_t)G->n, hipMemcpyDeviceToHost, slot.stream);
   if (e == hipSuccess) e = hipEventRecord(slot.done, slot.stream);
   if (e != hipSuccess) {
     r->status = SCAN_E_DEVICE;
@@ -259,6 +278,42 @@ bool launch_on_slot(scan_server* S, Slot& slot, const std::shared_ptr<Request>& 
   }
   G->inflight++;
   slot.req = r;
+  return true;
+}
+
+// A result buffer can be had (server lock held).
+bool out_available(const scan_server* S) { return !S->out_free.empty() || S->out_total < S->out_max; }
+
+// Gives the slot a result buffer of the current capacity if it has none
+// (server lock held); false when the pool is exhausted.
+bool acquire_out(scan_server* S, Slot& slot) {
+  if (slot.out.labels && slot.out.cap >= S->slot_n) return true;
+  if (slot.out.labels) {  // too small since the capacity grew
+    free_out(slot.out);
+    --S->out_total;
+  }
+  while (!S->out_free.empty()) {
+    OutBuf b = S->out_free.back();
+    S->out_free.pop_back();
+    if (b.cap >= S->slot_n) {
+      slot.out = b;
+      return true;
+    }
+    free_out(b);
+    --S->out_total;
+  }
+  if (S->out_total >= S->out_max) return false;
+  const size_t N = (size_t)(S->slot_n > 0 ? S->slot_n : 1);
+  OutBuf b;
+  if (hipHostMalloc((void**)&b.labels, 4 * N, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b.roles, N, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    free_out(b);
+    return false;
+  }
+  b.cap = S->slot_n;
+  slot.out = b;
+  ++S->out_total;
   return true;
 }
 
@@ -276,8 +331,10 @@ void worker_loop(scan_server* S) {
       ServedGraph* G = S->graphs[r->gid].get();
       G->inflight--;
       if (q == hipSuccess) {
-        r->labels.assign(slot.h_labels, slot.h_labels + G->n);
-        r->roles.assign(slot.h_roles, slot.h_roles + G->n);
+        // the buffer goes to the request; the slot takes another at its next admission
+        r->out = slot.out;
+        r->n = G->n;
+        slot.out = OutBuf();
         r->status = SCAN_OK;
       } else {
         r->status = SCAN_E_DEVICE;
@@ -311,6 +368,7 @@ void worker_loop(scan_server* S) {
           ++it;
           continue;
         }
+        if (!acquire_out(S, *free_slot)) break;  // every result buffer awaits collection
         if (!launch_on_slot(S, *free_slot, r, G)) finish(S, r);
       }
       it = S->pending.erase(it);
@@ -331,7 +389,10 @@ void worker_loop(scan_server* S) {
         std::this_thread::sleep_for(std::chrono::microseconds(20));
         lk.lock();
       } else {
-        S->cv_work.wait(lk, [&] { return S->stop || (!S->pending.empty() && !S->pause_dispatch); });
+        // woken by a submit, a returned result buffer, a resumed dispatch or a stop
+        S->cv_work.wait(lk, [&] {
+          return S->stop || (!S->pending.empty() && !S->pause_dispatch && out_available(S));
+        });
       }
     }
   }
@@ -363,6 +424,7 @@ int scan_server_create(const scan_opts* opts, int32_t num_slots, scan_server** o
   S->opts.hip_stream = nullptr;
   S->budget = S->opts.device_budget_bytes;
   S->slots.resize((size_t)num_slots);
+  S->out_max = 4 * num_slots + 16;
   for (auto& s : S->slots) {
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
@@ -551,6 +613,18 @@ int scan_server_wait(scan_server* S, int64_t req, int32_t* labels, uint8_t* role
   S->requests.erase(req);
   if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
   if (r->status != SCAN_OK) return fail(r->status, "%s", r->error.c_str());
+  if (r->out.labels) {
+    // copy out of the pinned buffer without the lock, then give it back
+    const OutBuf b = r->out;
+    r->out = OutBuf();
+    lk.unlock();
+    if (labels) memcpy(labels, b.labels, 4 * (size_t)r->n);
+    if (roles) memcpy(roles, b.roles, (size_t)r->n);
+    lk.lock();
+    S->out_free.push_back(b);
+    S->cv_work.notify_one();
+    return SCAN_OK;
+  }
   if (labels && !r->labels.empty()) memcpy(labels, r->labels.data(), 4 * r->labels.size());
   if (roles && !r->roles.empty()) memcpy(roles, r->roles.data(), r->roles.size());
   return SCAN_OK;
@@ -585,9 +659,12 @@ int scan_server_destroy(scan_server* S) {
   }
   for (auto& s : S->slots) {
     free_slot_buffers(s);
+    free_out(s.out);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);
   }
+  for (auto& b : S->out_free) free_out(b);
+  for (auto& kv : S->requests) free_out(kv.second->out);  // results never collected
   delete S;
   return SCAN_OK;
 }
