@@ -72,8 +72,9 @@ def main():
                     help="serving: arrivals of the plain comparison (bounded run)")
     ap.add_argument("--batch-count", type=int, default=10000)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy calibration")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="print the HBM traffic summary of two rocprofv3 --pmc runs of this bench")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="DIR",
+                    help="print the HBM traffic summary of rocprofv3 --pmc runs of this bench (FETCH_SIZE, "
+                         "WRITE_SIZE, read requests by size, DRAM requests)")
     ap.add_argument("--pmc-kernel", default="k_hub<0>")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -161,10 +162,16 @@ def main():
     csrc_ = S.scan_device_alloc(copy_bytes)
     cdst_ = S.scan_device_alloc(copy_bytes)
     copy_ms = S.scan_device_copy(cdst_, csrc_, copy_bytes, iters=5)
-    S.scan_device_free(csrc_)
+    read_bytes = 2 * copy_bytes  # the read-only stream covers both buffers
     S.scan_device_free(cdst_)
+    S.scan_device_free(csrc_)
     copy_gbps = 2.0 * copy_bytes / (copy_ms * 1e-3) / 1e9
-    log(f"streaming copy {args.copy_mib} MiB: {copy_ms:.3f} ms -> {copy_gbps:.0f} GB/s")
+    rbuf = S.scan_device_alloc(read_bytes)
+    read_ms = S.scan_device_read(rbuf, read_bytes, iters=5)
+    S.scan_device_free(rbuf)
+    read_gbps = read_bytes / (read_ms * 1e-3) / 1e9
+    log(f"streaming copy {args.copy_mib} MiB: {copy_ms:.3f} ms -> {copy_gbps:.0f} GB/s; "
+        f"read-only stream {read_bytes >> 20} MiB: {read_ms:.3f} ms -> {read_gbps:.0f} GB/s")
     dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
     traffic = _traffic_from_profile(dom_kernel)
     # every bucket's kernel against the same roofline, and the whole cores pass
@@ -273,7 +280,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"{dom_kernel}: cores pass, degree bucket {dom}",
-                     "copy_gbps": copy_gbps,
+                     "copy_gbps": copy_gbps, "read_gbps": read_gbps,
                      "launch_ms": float(ms_b[dom] / launches),
                      "alg_bytes_per_launch": float(bytes_b[dom] / launches)},
         "cpu_baseline": cpu,
@@ -338,7 +345,7 @@ def _traffic_from_profile(kernel):
 
 
 def _pmc_rows(d):
-    """(kernel name, counter, value) per dispatch from rocprofv3 counter CSVs under d."""
+    """(dispatch id, kernel name, counter, value) rows from rocprofv3 counter CSVs under d."""
     import csv
     import glob
     rows = []
@@ -358,21 +365,45 @@ def _per_dispatch_mean(rows, counter, match):
 
 
 def summarize_pmc(args):
-    """Markdown summary of HBM bytes per launch for the dominant kernel, scaled by the copy."""
-    fetch_rows = _pmc_rows(args.summarize_pmc[0])
-    write_rows = _pmc_rows(args.summarize_pmc[1])
-    is_copy = lambda nm: "k_copy16" in nm
+    """Markdown summary of HBM bytes per launch of the dominant kernel from
+    rocprofv3 counter runs of this bench (one directory per run): FETCH_SIZE
+    and WRITE_SIZE scaled by what they read for the plain copy kernel, the read
+    requests by size (32, 64, 128 bytes: bytes without any scaling) and the
+    share of read requests that went to DRAM."""
+    rows = []
+    for d in args.summarize_pmc:
+        rows += _pmc_rows(d)
+    is_copy = lambda nm: "k_copy16" in nm  # noqa: E731
     want = args.pmc_kernel
-    is_k = lambda nm: want in nm
-    cf, ncf = _per_dispatch_mean(fetch_rows, "FETCH_SIZE", is_copy)
-    cw, ncw = _per_dispatch_mean(write_rows, "WRITE_SIZE", is_copy)
-    kf, nkf = _per_dispatch_mean(fetch_rows, "FETCH_SIZE", is_k)
-    kw, nkw = _per_dispatch_mean(write_rows, "WRITE_SIZE", is_k)
+    is_k = lambda nm: want in nm  # noqa: E731
+    got = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+              "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_DRAM_sum"):
+        got[c] = (_per_dispatch_mean(rows, c, is_copy), _per_dispatch_mean(rows, c, is_k))
+    (cf, ncf), (kf, nkf) = got["FETCH_SIZE"]
+    (cw, ncw), (kw, nkw) = got["WRITE_SIZE"]
     if None in (cf, cw, kf, kw):
         sys.exit(f"missing dispatches: copy {ncf}/{ncw}, {want} {nkf}/{nkw}")
     copy_kib = (args.copy_mib << 20) / 1024.0
     sf, sw = copy_kib / cf, copy_kib / cw
-    traffic = (kf * sf + kw * sw) * 1024.0
+    fetch_scaled = kf * sf * 1024.0
+    write_bytes = kw * sw * 1024.0
+
+    def by_size(which):
+        vals = [got[c][which][0] for c in ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")]
+        return None if None in vals else 32.0 * vals[0] + 64.0 * vals[1] + 128.0 * vals[2]
+
+    read_copy, read_k = by_size(0), by_size(1)
+    read_bytes = read_k if read_k is not None else fetch_scaled
+    traffic = read_bytes + write_bytes
+    dram = got["TCC_EA0_RDREQ_DRAM_sum"][1][0]
+    req = got["TCC_EA0_RDREQ_sum"][1][0]
+    cmd = "python bench.py --summarize-pmc " + " ".join(args.summarize_pmc) + f" --pmc-kernel '{want}'"
+    size_rows = ""
+    for label, which in (("k_copy16", 0), (want, 1)):
+        vals = [got[c][which][0] for c in ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+                                            "TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_DRAM_sum")]
+        size_rows += "| " + label + " | " + " | ".join("-" if v is None else f"{v:.4g}" for v in vals) + " |\n"
     print(f"""# HBM traffic of {want} (cores pass, LDS-hash bucket), R-MAT scale 22
 
 Commands (from the repository root on the MI355X host, each its own run):
@@ -380,18 +411,29 @@ Commands (from the repository root on the MI355X host, each its own run):
 ```
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
-python bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --pmc-kernel '{want}'
+rocprofv3 --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_rdreq -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
+rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_dram -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
+{cmd}
 ```
 
-The copy kernel `k_copy16` moves {args.copy_mib} MiB (read once, written once) per dispatch; its
-counters scale the kernel's (KiB per dispatch, mean over dispatches).
+The copy kernel `k_copy16` moves {args.copy_mib} MiB (read once, written once) per dispatch; FETCH_SIZE
+and WRITE_SIZE of the kernel are scaled by what they read for it (KiB per dispatch, mean over dispatches).
 
 | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |
 |---|---|---|---|
 | k_copy16 | {ncf}/{ncw} | {cf:.0f} | {cw:.0f} |
 | {want} | {nkf}/{nkw} | {kf:.0f} | {kw:.0f} |
 
-- copy scale (fetch, write): {sf:.4f}, {sw:.4f}
+Read requests by size (per dispatch; bytes = 32 n32 + 64 n64 + 128 n128, no scaling), all requests, and
+those that went to DRAM:
+
+| kernel | 32 B | 64 B | 128 B | all | to DRAM |
+|---|---|---|---|---|---|
+{size_rows}
+- copy: read bytes by request size {"-" if read_copy is None else f"{read_copy:.4g}"} (moved: {args.copy_mib << 20}); FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f}
+- kernel read bytes: by request size {"-" if read_k is None else f"{read_k:.4g}"}, by scaled FETCH_SIZE {fetch_scaled:.4g}
+- kernel write bytes (scaled WRITE_SIZE): {write_bytes:.4g}
+- read requests that went to DRAM: {"-" if dram is None or not req else f"{dram / req:.3f}"}
 - kernel: `{want}`
 - kernel_sources_sha256: `{_kernel_source_hash()}`
 - traffic_bytes_per_launch: {traffic:.0f}
@@ -435,6 +477,7 @@ def bench_partitioned(args):
         same = bool(np.array_equal(pl, ml) and np.array_equal(pr, mr))
         exact = exact and same
         rows.append({"eps": f"{p}/{q}", "mu": mu, "partitioned_s": tp, "in_memory_s": tm,
+                     "partitioned_ms_phase": st["ms_phase"],
                      "partitioned_edges_per_s": g.m / tp, "in_memory_edges_per_s": g.m / tm,
                      "h2d_GB": st["h2d_bytes"] / 1e9, "h2d_GB_per_s": st["h2d_bytes"] / 1e9 / tp,
                      "identical_to_in_memory": same, "cores": int((pr == 1).sum()),

@@ -209,6 +209,9 @@ typedef struct scan_stats {
   int64_t cores_bucket_evaluated[SCAN_NUM_BUCKETS];
   int64_t cores_bucket_probes[SCAN_NUM_BUCKETS];
   int64_t h2d_bytes;                      /* partitioned path: bytes streamed to the device */
+  int64_t group_split;                    /* LDS-hash kernel: lanes that claimed another chunk than
+                                             their group (a group's lanes must stay together);
+                                             always 0 in a correct run */
 } scan_stats;
 
 int scan_last_stats(const scan_graph* g, scan_stats* out);
@@ -343,6 +346,14 @@ int scan_memcpy_h2d(void* dst, const void* src, uint64_t bytes);
  * clustering kernels are calibrated.  SCAN_E_INVAL on a bad size, alignment
  * or iteration count. */
 int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, float* avg_ms);
+
+/* Read-only stream of `bytes` (a multiple of 16) from the device buffer src
+ * (16-byte aligned) by a plain streaming kernel, `iters` >= 1 times in a row;
+ * *avg_ms (may be NULL) receives the mean kernel time.  Not part of the
+ * clustering path: the achievable rate of a kernel that only reads, the
+ * ceiling for the intersection kernels (which write almost nothing).
+ * SCAN_E_INVAL on a bad size, alignment or iteration count. */
+int scan_device_read(const void* src, uint64_t bytes, int32_t iters, float* avg_ms);
 
 /* Host-to-device link rate: copies `bytes` from a pinned host buffer into a
  * device buffer (both allocated and freed inside the call) `iters` >= 1 times

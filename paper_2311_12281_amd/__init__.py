@@ -33,7 +33,7 @@ EXPORTED = [
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
     "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint", "scan_batch_set_params",
-    "scan_server_set_budget",
+    "scan_server_set_budget", "scan_device_read",
 ]
 
 
@@ -87,6 +87,7 @@ class scan_stats(ctypes.Structure):
         ("cores_bucket_evaluated", ctypes.c_int64 * NUM_BUCKETS),
         ("cores_bucket_probes", ctypes.c_int64 * NUM_BUCKETS),
         ("h2d_bytes", ctypes.c_int64),
+        ("group_split", ctypes.c_int64),
     ]
 
 
@@ -122,6 +123,7 @@ def lib():
         L.scan_memcpy_d2h.argtypes = [vp, vp, u64]
         L.scan_memcpy_h2d.argtypes = [vp, vp, u64]
         L.scan_device_copy.argtypes = [vp, vp, u64, i32, P(ctypes.c_float)]
+        L.scan_device_read.argtypes = [vp, u64, i32, P(ctypes.c_float)]
         L.scan_h2d_rate.argtypes = [u64, i32, P(ctypes.c_double)]
         L.scan_server_create.argtypes = [P(scan_opts), i32, P(vp)]
         L.scan_server_add_graph.argtypes = [vp, i32, i64, vp, vp, P(i32)]
@@ -147,7 +149,8 @@ def lib():
                      "scan_server_submit", "scan_server_wait", "scan_server_info", "scan_server_destroy",
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
                      "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc",
-                     "scan_graph_footprint", "scan_batch_set_params", "scan_server_set_budget"):
+                     "scan_graph_footprint", "scan_batch_set_params", "scan_server_set_budget",
+                     "scan_device_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -275,6 +278,7 @@ def scan_last_stats(g) -> dict:
         "cores_bucket_evaluated": list(s.cores_bucket_evaluated),
         "cores_bucket_probes": list(s.cores_bucket_probes),
         "h2d_bytes": s.h2d_bytes,
+        "group_split": s.group_split,
     }
 
 
@@ -303,6 +307,13 @@ def scan_device_copy(dst: int, src: int, nbytes: int, iters: int = 1) -> float:
     ms = ctypes.c_float()
     _check(lib().scan_device_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), int(nbytes), int(iters),
                                   ctypes.byref(ms)))
+    return float(ms.value)
+
+
+def scan_device_read(src: int, nbytes: int, iters: int = 1) -> float:
+    """Streaming read-only kernel over a device buffer; returns the mean kernel time in ms."""
+    ms = ctypes.c_float()
+    _check(lib().scan_device_read(ctypes.c_void_p(src), int(nbytes), int(iters), ctypes.byref(ms)))
     return float(ms.value)
 
 

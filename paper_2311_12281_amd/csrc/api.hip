@@ -153,6 +153,7 @@ int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
     L.cores_bucket_evaluated[k] = (int64_t)st[ST_BUCKET_EVAL + k];
     L.cores_bucket_probes[k] = (int64_t)st[ST_BUCKET_PROBES + k];
   }
+  L.group_split = (int64_t)st[ST_GROUP_SPLIT];
   const int phase_of_mode[4] = {SCAN_PHASE_CORES, SCAN_PHASE_MERGE, SCAN_PHASE_ATTACH, SCAN_PHASE_CORES};
   for (int md = 0; md < 3; ++md) {
     L.evaluated[phase_of_mode[md]] = (int64_t)st[ST_EVAL + md];
@@ -251,6 +252,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   memset(&L, 0, sizeof(L));
   L.edges = g->m;
   L.evaluated[SCAN_PHASE_CORES] = (int64_t)st[ST_EVAL + MODE_COUNTS];
+  L.group_split = (int64_t)st[ST_GROUP_SPLIT];
   L.probes[SCAN_PHASE_CORES] = (int64_t)st[ST_PROBES + MODE_COUNTS];
   for (int k = 0; k < kNumBuckets; ++k) L.bucket_edges[k] = g->bucket_off[k + 1] - g->bucket_off[k];
   if (timing) {
@@ -335,6 +337,7 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     CTRY(dalloc(&g->d_parent, n), "hipMalloc");
     CTRY(dalloc(&g->d_label, n), "hipMalloc");
     CTRY(dalloc(&g->d_stats, ST_COUNT), "hipMalloc");
+    CTRY(dalloc(&g->d_counters, kCounters), "hipMalloc");
     for (auto& ev : g->ev) CTRY(hipEventCreate(&ev), "hipEventCreate");
     CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
     *out = g;
@@ -536,6 +539,34 @@ int scan_device_copy(void* dst, const void* src, uint64_t bytes, int32_t iters, 
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(s);
+  if (rc == SCAN_OK && avg_ms) *avg_ms = ms / (float)iters;
+  return rc;
+}
+
+int scan_device_read(const void* src, uint64_t bytes, int32_t iters, float* avg_ms) {
+  if (!src || (bytes & 15) || iters < 1 || ((uintptr_t)src & 15))
+    return fail(SCAN_E_INVAL, "scan_device_read: bytes must be a multiple of 16, src 16-byte aligned, iters >= 1");
+  uint32_t* sink = nullptr;
+  HIP_TRY(hipMalloc((void**)&sink, sizeof(uint32_t) * (size_t)read16_sink_words()), "hipMalloc");
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SCAN_OK;
+  float ms = 0.f;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    rc = fail(SCAN_E_DEVICE, "scan_device_read: stream or event creation failed");
+  } else {
+    (void)hipEventRecord(e0, s);
+    for (int32_t i = 0; i < iters; ++i) launch_read16(s, src, (int64_t)(bytes / 16), sink);
+    (void)hipEventRecord(e1, s);
+    hipError_t err = hipStreamSynchronize(s);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) rc = fail_hip(err, "scan_device_read");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(sink);
   if (rc == SCAN_OK && avg_ms) *avg_ms = ms / (float)iters;
   return rc;
 }

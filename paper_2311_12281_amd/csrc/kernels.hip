@@ -741,6 +741,7 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
   const bool exact = (MODE == MODE_COUNTS) || !A.pruning;
   const int4* T4 = reinterpret_cast<const int4*>(table);
   unsigned long long n_eval = 0, n_bound = 0, n_probe = 0;
+  uint32_t n_split = 0;
   if ((MODE == MODE_MERGE || MODE == MODE_ATTACH) && A.ncores && *A.ncores == 0) return;  // no cluster
   while (true) {
     if (tid == 0) {
@@ -905,12 +906,22 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
             const int32_t* Arow = A.hci + q_bu[tid];
             int32_t lo = q_pos[tid], hi2 = q_du[tid];
             if (hi != INT_MAX) {
-              while (lo < hi2) {
-                const int32_t mid = (lo + hi2) >> 1;
-                if (Arow[mid] < hi) lo = mid + 1;
-                else hi2 = mid;
+              // first element >= hi, found by galloping from the survivor's
+              // position (Arow[lo] < hi): the probes fall on lines of this
+              // window's part, which the chunks read next, and at most one past it
+              int64_t a = lo, b = hi2, step = 32;
+              while (a + step < b && Arow[a + step] < hi) {
+                a += step;
+                step *= 2;
               }
-              q_end[tid] = lo;
+              if (a + step < b) b = a + step;
+              ++a;  // Arow[a - 1] < hi
+              while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                if (Arow[mid] < hi) a = mid + 1;
+                else b = mid;
+              }
+              q_end[tid] = (int32_t)a;
             } else {
               q_end[tid] = hi2;
             }
@@ -968,6 +979,10 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
           // the group's chunk (a uniform addend keeps this a single atomic per
           // wave and avoids any branch on the lane index)
           const int32_t c = atomicAdd(&s_chunk, 1) / kHubGroup;
+          // every lane of a group must have the same chunk (the shuffles below
+          // read the group's lanes); a lane that does not is counted, without
+          // a branch, and the parity tests require the count to stay zero
+          n_split += (c != __shfl(c, (tid & 63) & ~(kHubGroup - 1), 64)) ? 1u : 0u;
           if (c >= n_chunks) break;
           const bool first = c < n_first;
           const int32_t cc = first ? c : c - n_first;
@@ -1146,6 +1161,8 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
     }
     __syncthreads();  // every thread is done with this job's shared values
   }
+  const unsigned long long splits = wave_sum(n_split);
+  if ((tid & 63) == 0 && splits) atomicAdd(A.stats + ST_GROUP_SPLIT, splits);
   flush_stats(A, MODE, n_eval, n_bound, n_probe);
 }
 
@@ -1160,6 +1177,20 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+// Plain streaming read, 16 bytes per lane per step, folded into one word per
+// thread (written so that the reads are not removed): the achievable rate of a
+// read-only stream, the ceiling for kernels that mostly read.
+__global__ void k_read16(const uint4* __restrict__ src, int64_t n16, uint32_t* __restrict__ sink) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (; i < n16; i += stride) {
+    const uint4 v = src[i];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
 __global__ void k_init(int32_t n, const int64_t* rp, int32_t mu, const int32_t* gid, const int32_t* gmu,
@@ -1718,6 +1749,12 @@ void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, 
 
 void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16) {
   if (n16 > 0) k_copy16<<<blocks_for(n16, 256, 16384), 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+}
+
+int read16_sink_words() { return 16384 * 256; }
+
+void launch_read16(hipStream_t s, const void* src, int64_t n16, uint32_t* sink) {
+  if (n16 > 0) k_read16<<<blocks_for(n16, 256, 16384), 256, 0, s>>>((const uint4*)src, n16, sink);
 }
 
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n) {

@@ -344,11 +344,28 @@ void select_chunks(const PartPlan& P, const uint8_t* role, std::vector<int32_t>&
   const size_t nc = P.chunks.size();
   std::vector<uint8_t> need_m(nc, 0), need_a(nc, 0);
   const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  // blocks holding a core: a chunk whose two blocks hold none has nothing to do
+  const int32_t K = (int32_t)P.block_lo.size() - 1;
+  std::vector<uint8_t> block_core((size_t)(K > 0 ? K : 1), 0);
+  {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        for (int32_t b = (int32_t)t; b < K; b += (int32_t)nth)
+          for (int32_t v = P.block_lo[(size_t)b]; v < P.block_lo[(size_t)b + 1]; ++v)
+            if (role[v] == ROLE_CORE) {
+              block_core[(size_t)b] = 1;
+              break;
+            }
+      });
+    for (auto& x : th) x.join();
+  }
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nth; ++t)
     th.emplace_back([&, t]() {
       for (size_t c = t; c < nc; c += nth) {
         const PartChunk& C = P.chunks[c];
+        if (!block_core[(size_t)C.bi] && !block_core[(size_t)C.bj]) continue;
         bool m = false, a = false;
         for (int64_t e = C.begin; e < C.end && !(m && a); ++e) {
           const int2 uv = P.h_edges[e];
@@ -398,7 +415,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
   A.pruning = g->opts.pruning;
   mark(0);
   launch_init(s, n, g->d_rp, mu, g->d_lower, g->d_upper, g->d_role, g->d_parent);
-  if (g->m > 0) memset(P.h_state, SIM_UNK, (size_t)g->m);
+  launch_zero_u64(s, g->d_counters, kCounters);
   mark(1);
   // Chunks each pass streams: all of them for the cores pass; after it, only
   // those holding an edge the pass can act on (merge: both endpoints cores;
@@ -412,12 +429,17 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
     const int mode = modes[mi];
     if (mode == MODE_MERGE) {
       mark(2);
-      launch_finalize_roles(s, n, mu, g->d_lower, g->d_role);
+      launch_finalize_roles(s, n, mu, g->d_lower, g->d_role, nullptr, nullptr, g->d_counters + 4);
       mark(3);
-      std::vector<uint8_t> role((size_t)n);
-      if (n > 0) HIP_TRY(hipMemcpyAsync(role.data(), g->d_role, (size_t)n, hipMemcpyDeviceToHost, s), "roles D2H");
+      unsigned long long ncores = 0;
+      HIP_TRY(hipMemcpyAsync(&ncores, g->d_counters + 4, sizeof(ncores), hipMemcpyDeviceToHost, s), "cores D2H");
       HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-      select_chunks(P, role.data(), merge_list, attach_list);
+      if (ncores > 0) {  // no core: no cluster, and the merge and attach passes have nothing to do
+        std::vector<uint8_t> role((size_t)n);
+        if (n > 0) HIP_TRY(hipMemcpyAsync(role.data(), g->d_role, (size_t)n, hipMemcpyDeviceToHost, s), "roles D2H");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        select_chunks(P, role.data(), merge_list, attach_list);
+      }
       mark(4);
     } else if (mode == MODE_ATTACH) {
       mark(5);
@@ -433,19 +455,22 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
       const int b = idx & 1;
       int2* de = b ? P.d_edges2 : P.d_edges;
       uint8_t* ds = b ? P.d_state2 : P.d_state;
-      // upload on the copy stream once the chunk that last used this buffer is done
+      // upload on the copy stream once the chunk that last used this buffer is done;
+      // the cores pass starts every state at ? on the device (nothing to send)
       if (idx >= 2) HIP_TRY(hipStreamWaitEvent(P.copy, P.done[b], 0), "hipStreamWaitEvent");
       HIP_TRY(hipMemcpyAsync(de, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, P.copy),
               "edges H2D");
-      HIP_TRY(hipMemcpyAsync(ds, P.h_state + C.begin, (size_t)ne, hipMemcpyHostToDevice, P.copy), "state H2D");
+      if (mode != MODE_CORES)
+        HIP_TRY(hipMemcpyAsync(ds, P.h_state + C.begin, (size_t)ne, hipMemcpyHostToDevice, P.copy), "state H2D");
       HIP_TRY(hipEventRecord(P.up[b], P.copy), "hipEventRecord");
-      P.h2d_bytes += 9ull * (uint64_t)ne;
+      P.h2d_bytes += (mode != MODE_CORES ? 9ull : 8ull) * (uint64_t)ne;
       ++P.chunks_streamed;
       // block rows go on the compute stream: the previous chunk's kernels read the old ones
       HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
       HIP_TRY(hipStreamWaitEvent(s, P.up[b], 0), "hipStreamWaitEvent");
       A.edges = de;
       A.state = ds;
+      if (mode == MODE_CORES) launch_fill_u8(s, ds, ne, SIM_UNK);
       if (mode == MODE_MERGE) launch_hook(s, ne, de, ds, g->d_role, g->d_parent);
       launch_chunk(s, mode, C, A, P);
       if (mode != MODE_ATTACH)
@@ -489,6 +514,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
     L.cores_bucket_probes[k] = (int64_t)stv[ST_BUCKET_PROBES + k];
   }
   L.h2d_bytes = (int64_t)P.h2d_bytes;
+  L.group_split = (int64_t)stv[ST_GROUP_SPLIT];
   if (timing) {
     float ms = 0;
     for (int ph = 0; ph < SCAN_NUM_PHASES; ++ph) {
@@ -545,9 +571,12 @@ int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
       }
     });
   for (auto& x : th) x.join();
+  unsigned long long stv[ST_COUNT];
+  HIP_TRY(hipMemcpy(stv, g->d_stats, sizeof(stv), hipMemcpyDeviceToHost), "stats copy");
   g->last = scan_stats();
   g->last.edges = m;
   g->last.h2d_bytes = (int64_t)P.h2d_bytes;
+  g->last.group_split = (int64_t)stv[ST_GROUP_SPLIT];
   return SCAN_OK;
 }
 

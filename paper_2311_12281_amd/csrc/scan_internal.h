@@ -41,7 +41,8 @@ enum : int {
   ST_PROBES = 8,    // + phase: smaller-list elements consumed
   ST_BUCKET_EVAL = 12,   // + bucket (cores phase only)
   ST_BUCKET_PROBES = 19, // + bucket
-  ST_COUNT = 26
+  ST_GROUP_SPLIT = 26,   // LDS-hash kernel: lanes of a group that claimed a different chunk than the group's first lane
+  ST_COUNT = 27
 };
 // Mode -> stats phase slot (0..3).
 __host__ __device__ inline int mode_slot(int mode) { return mode; }
@@ -155,6 +156,9 @@ void launch_hub(hipStream_t s, int mode, const EdgeArgs& a, const HubJob* jobs, 
 int hub_grid_blocks();
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n);
 void launch_copy16(hipStream_t s, const void* src, void* dst, int64_t n16);
+// Read-only stream of n16 16-byte words; sink holds read16_sink_words() words.
+void launch_read16(hipStream_t s, const void* src, int64_t n16, uint32_t* sink);
+int read16_sink_words();
 void launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
 // ncores (optional): incremented by the number of cores after the pass.
 void launch_finalize_roles(hipStream_t s, int32_t n, int32_t mu, const int32_t* lower, uint8_t* role,

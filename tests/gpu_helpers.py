@@ -11,14 +11,24 @@ def note(*args):
     print("[gpu-case]", *args, flush=True)
 
 
+def assert_groups_whole(G, ctx=""):
+    """The LDS-hash kernel's groups of lanes must each claim one chunk together."""
+    split = G.stats()["group_split"]
+    assert split == 0, f"{ctx}: {split} lanes claimed a chunk apart from their group"
+
+
 def gpu_run(g, p, q, mu, **opts):
     with S.Graph.from_csr(g, **opts) as G:
-        return G.run(p, q, mu)
+        out = G.run(p, q, mu)
+        assert_groups_whole(G, f"run eps={p}/{q} mu={mu}")
+        return out
 
 
 def gpu_counts(g, **opts):
     with S.Graph.from_csr(g, **opts) as G:
-        return G.similarity()
+        out = G.similarity()
+        assert_groups_whole(G, "similarity")
+        return out
 
 
 def assert_same(gl, gr, ol, orr, ctx=""):

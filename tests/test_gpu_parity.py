@@ -10,7 +10,7 @@ import graphgen as gg
 import oracle
 import paper_2311_12281_amd as S
 import pins
-from gpu_helpers import assert_same, gpu_counts, gpu_run, note
+from gpu_helpers import assert_groups_whole, assert_same, gpu_counts, gpu_run, note
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,7 @@ def check_graph(g, params, name, counts=True, **opts):
         for (p, q), mu in params:
             note(name, f"eps={p}/{q} mu={mu}")
             gl, gr = G.run(p, q, mu)
+            assert_groups_whole(G, f"{name} eps={p}/{q} mu={mu}")
             if oc is not None:
                 ol, orr = oracle.cluster(g, oc, p, q, mu)
             else:

@@ -7,7 +7,7 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_2311_12281_amd as S
-from gpu_helpers import assert_same, note
+from gpu_helpers import assert_groups_whole, assert_same, note
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +103,7 @@ def test_partitioned_hub_windows_in_a_later_block(name):
             assert P.stats()["h2d_bytes"] > g.nnz * 4  # rows were streamed
             for (p, q), mu in params:
                 gl, gr = P.run(p, q, mu)
+                assert_groups_whole(P, f"partitioned {name} eps={p}/{q} mu={mu}")
                 ol, orr = oracle.cluster(g, oc, p, q, mu)
                 assert_same(gl, gr, ol, orr, f"partitioned {name} eps={p}/{q} mu={mu}")
 
