@@ -43,7 +43,7 @@ namespace {
 
 void release(scan_graph* g) {
   part_release(g);
-  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_edeg, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -96,6 +96,7 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
   A.wtab = g->d_wtab;
+  A.edeg = g->d_edeg;
   A.state = R.state;
   A.lower = R.lower;
   A.upper = R.upper;
@@ -180,7 +181,7 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   if (g->partitioned) return 0;
   const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, m = (uint64_t)g->m;
   const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
-  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
+  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 16 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
                4 * (uint64_t)g->wtab_entries;
   if (g->d_hci) b += 4 * (nnz + kColPad);
   b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
@@ -382,6 +383,9 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
     rc = fail(SCAN_E_GRAPH, "edge count %lld does not match nnz/2", (long long)g->m);
     goto error;
   }
+  CTRY(dalloc(&g->d_edeg, g->m), "hipMalloc edge degrees");
+  launch_edge_degrees(g->stream, g->m, g->d_rp, g->d_edges, g->d_edeg);
+  CTRY(hipGetLastError(), "edge degrees");
   CTRY(dalloc(&g->d_lower, n), "hipMalloc");
   CTRY(dalloc(&g->d_upper, n), "hipMalloc");
   CTRY(dalloc(&g->d_role, n), "hipMalloc");

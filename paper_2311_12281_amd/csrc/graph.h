@@ -68,6 +68,7 @@ struct scan_graph {
   HubJob* d_jobs = nullptr;
   int64_t hub_jobs = 0;
   uint32_t* d_wtab = nullptr;     // LDS-hash windows of the jobs' larger sides
+  int2* d_edeg = nullptr;         // degrees of both sides per oriented edge
   int64_t wtab_entries = 0;
   int32_t* d_worklist = nullptr;  // one slot per edge of the last bucket
   // per-run state

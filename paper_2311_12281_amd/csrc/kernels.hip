@@ -133,12 +133,18 @@ __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool acti
   const int2 uv = A.edges[e];
   ev.u = uv.x;
   ev.v = uv.y;
-  ev.du = A.rp[ev.u + 1] - A.rp[ev.u];
-  ev.dv = A.rp[ev.v + 1] - A.rp[ev.v];
-  ev.bu = row_start(A, ev.u);
-  ev.bv = row_start(A, ev.v);
+  if (A.edeg) {  // both degrees with the edge: no row offsets unless the edge is intersected
+    const int2 d = A.edeg[e];
+    ev.du = d.x;
+    ev.dv = d.y;
+  } else {
+    ev.du = A.rp[ev.u + 1] - A.rp[ev.u];
+    ev.dv = A.rp[ev.v + 1] - A.rp[ev.v];
+  }
   const uint64_t a = (uint64_t)ev.du + 1, b = (uint64_t)ev.dv + 1;
   if (MODE == MODE_COUNTS) {
+    ev.bu = row_start(A, ev.u);
+    ev.bv = row_start(A, ev.v);
     ev.need = 0;
     ev.work = 1;
     return;
@@ -177,6 +183,8 @@ __device__ __forceinline__ void classify(const EdgeArgs& A, int64_t e, bool acti
     return;
   }
   ev.need = (int32_t)closed_needed(p, q, a, b);
+  ev.bu = row_start(A, ev.u);
+  ev.bv = row_start(A, ev.v);
   ev.work = 1;
 }
 
@@ -979,10 +987,15 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
           // the group's chunk (a uniform addend keeps this a single atomic per
           // wave and avoids any branch on the lane index)
           const int32_t c = atomicAdd(&s_chunk, 1) / kHubGroup;
-          // every lane of a group must have the same chunk (the shuffles below
-          // read the group's lanes); a lane that does not is counted, without
-          // a branch, and the parity tests require the count to stay zero
-          n_split += (c != __shfl(c, (tid & 63) & ~(kHubGroup - 1), 64)) ? 1u : 0u;
+          // every lane of a group must have the same chunk (the totals below
+          // are read back for the whole group); each lane compares its chunk
+          // with its left neighbour's (one DPP row shift, no branch), and a
+          // lane whose neighbour in the group differs is counted.  All seven
+          // neighbour pairs equal means the whole group agrees; the parity
+          // tests require the count to stay zero.
+          static_assert(kHubGroup <= 16, "a group lies in one DPP row");
+          const int32_t left = __builtin_amdgcn_update_dpp(c, c, 0x111 /* row_shr:1 */, 0xF, 0xF, false);
+          n_split += ((tid & (kHubGroup - 1)) != 0 && left != c) ? 1u : 0u;
           if (c >= n_chunks) break;
           const bool first = c < n_first;
           const int32_t cc = first ? c : c - n_first;
@@ -1164,6 +1177,15 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
   const unsigned long long splits = wave_sum(n_split);
   if ((tid & 63) == 0 && splits) atomicAdd(A.stats + ST_GROUP_SPLIT, splits);
   flush_stats(A, MODE, n_eval, n_bound, n_probe);
+}
+
+__global__ void k_edge_degrees(int64_t m, const int64_t* rp, const int2* edges, int2* deg) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < m; e += stride) {
+    const int2 uv = edges[e];
+    deg[e] = make_int2((int32_t)(rp[uv.x + 1] - rp[uv.x]), (int32_t)(rp[uv.y + 1] - rp[uv.y]));
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -1755,6 +1777,10 @@ int read16_sink_words() { return 16384 * 256; }
 
 void launch_read16(hipStream_t s, const void* src, int64_t n16, uint32_t* sink) {
   if (n16 > 0) k_read16<<<blocks_for(n16, 256, 16384), 256, 0, s>>>((const uint4*)src, n16, sink);
+}
+
+void launch_edge_degrees(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, int2* deg) {
+  if (m > 0) k_edge_degrees<<<blocks_for(m, 256, 16384), 256, 0, s>>>(m, rp, edges, deg);
 }
 
 void launch_zero_u64(hipStream_t s, unsigned long long* p, int n) {

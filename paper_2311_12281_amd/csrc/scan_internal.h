@@ -111,6 +111,7 @@ struct EdgeArgs {
   const int32_t* hci;  // rows read by the LDS-hash kernel: ci, or ci renamed by degree rank
   const int2* edges;  // oriented: x = smaller side (deg, id), y = larger side
   const uint32_t* wtab;  // LDS-hash windows of the jobs' larger sides (HubJob::wbeg)
+  const int2* edeg;   // degrees of both sides per oriented edge (null: read from rp)
   int64_t e_begin, e_end;
   uint8_t* state;     // per oriented edge
   int32_t* lower;     // confirmed |N_eps| lower bound (starts at 1)
@@ -254,6 +255,9 @@ void launch_batch_edge_offsets(hipStream_t s, int32_t G, const int64_t* vtx_off,
                                const int64_t* bucket_off_host, int64_t* eoff);
 // Blocks of the persistent kernel that fit on the device at once.
 int batch_grid_blocks();
+
+// deg[e] = (degree of edges[e].x, degree of edges[e].y) for m oriented edges.
+void launch_edge_degrees(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, int2* deg);
 
 // Layout (layout.hip)
 struct LayoutResult {
