@@ -232,10 +232,12 @@ __device__ __forceinline__ bool load_survivor(const EdgeArgs& A, int64_t e, Edge
 // never changes, and the final count is read only for roles still unknown.
 // The upper bound is kept only for degrees up to kUpperMaxDegree: it serves
 // just to mark a vertex non-core early (Lemma 4.1), which for a vertex of
-// higher degree happens only after nearly all of its edges were tested, while
-// every one of its edges would update the same counter.  Such a vertex keeps
-// role ? and is settled from its exact lower bound at the end of the pass.
-constexpr int64_t kUpperMaxDegree = 256;
+// higher degree happens only after most of its edges were tested, while every
+// one of its dissimilar edges costs a device-scope atomic on that vertex's
+// counter; the few intersections an early mark saves do not pay for those
+// beyond a few dozen neighbours.  Such a vertex keeps role ? and is settled
+// from its exact lower bound at the end of the pass.
+constexpr int64_t kUpperMaxDegree = 16;
 static_assert(kUpperMaxDegree < kHubMinDegree, "the LDS-hash kernel keeps no upper bound for its larger side");
 __device__ __forceinline__ void cores_count(const EdgeArgs& A, const EdgeView& ev, bool sim, bool do_u,
                                             bool do_v, int32_t& cu, int32_t& cv) {
@@ -298,6 +300,40 @@ __device__ __forceinline__ void flush_stats(const EdgeArgs& A, int mode, unsigne
   bd = wave_sum(bd);
   pr = wave_sum(pr);
   if ((threadIdx.x & 63) == 0) {
+    if (ev) atomicAdd(A.stats + ST_EVAL + mode, ev);
+    if (bd) atomicAdd(A.stats + ST_BOUND + mode, bd);
+    if (pr) atomicAdd(A.stats + ST_PROBES + mode, pr);
+    if (mode == MODE_CORES) {
+      if (ev) atomicAdd(A.stats + ST_BUCKET_EVAL + A.bucket, ev);
+      if (pr) atomicAdd(A.stats + ST_BUCKET_PROBES + A.bucket, pr);
+    }
+  }
+}
+
+// The same totals summed over the block first (every thread of the block must
+// call it): one set of atomics per block instead of one per wave, since many
+// short-lived waves adding to the same few counters serialise on them.
+template <int NW>
+__device__ __forceinline__ void flush_stats_block(const EdgeArgs& A, int mode, unsigned long long ev,
+                                                  unsigned long long bd, unsigned long long pr) {
+  __shared__ unsigned long long part[3][NW];
+  ev = wave_sum(ev);
+  bd = wave_sum(bd);
+  pr = wave_sum(pr);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][w] = ev;
+    part[1][w] = bd;
+    part[2][w] = pr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ev = bd = pr = 0;
+    for (int k = 0; k < NW; ++k) {
+      ev += part[0][k];
+      bd += part[1][k];
+      pr += part[2][k];
+    }
     if (ev) atomicAdd(A.stats + ST_EVAL + mode, ev);
     if (bd) atomicAdd(A.stats + ST_BOUND + mode, bd);
     if (pr) atomicAdd(A.stats + ST_PROBES + mode, pr);
@@ -555,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_group(EdgeArgs A) {
   PassCounts pc;
   group_edges<MODE, G, STAGE>(A, A.e_begin, A.e_end, wave, nwaves, stage + (STAGE ? (threadIdx.x >> 6) * kWaveSlots : 0),
                               pc);
-  flush_stats(A, MODE, pc.eval, pc.bound, pc.probe);
+  flush_stats_block<kBlock / 64>(A, MODE, pc.eval, pc.bound, pc.probe);
 }
 
 // Last bucket (d_u > 64), grouped by the larger side v.  A job is up to
@@ -1679,11 +1715,17 @@ inline unsigned blocks_for(int64_t items, int64_t per_block, int64_t cap) {
   return (unsigned)b;
 }
 
+// Grid-size caps of the group buckets (blocks of kBlock threads; a smaller
+// grid makes each wave loop over several 64-edge chunks).  The buckets of the
+// shortest lists are latency-bound on per-vertex state, where fewer, longer-
+// lived waves do better; the wider groups keep more waves in flight.
+constexpr int64_t kGroupGridCap[kNumBuckets] = {2048, 2048, 4096, 8192, 8192, 8192, 8192};
+
 template <int MODE>
 void launch_edges_mode(hipStream_t s, int bucket, const EdgeArgs& a) {
   const int64_t m = a.e_end - a.e_begin;
   if (m <= 0) return;
-  const unsigned grid = blocks_for(m, kBlock, 8192);
+  const unsigned grid = blocks_for(m, kBlock, kGroupGridCap[bucket >= 0 && bucket < kNumBuckets ? bucket : kNumBuckets - 1]);
   switch (bucket) {
     case 0: k_group<MODE, 4><<<grid, kBlock, 0, s>>>(a); break;
     case 1: k_group<MODE, 8><<<grid, kBlock, 0, s>>>(a); break;
