@@ -114,7 +114,7 @@ int scan_graph_destroy(scan_graph* g);
 /* Upper bound of the device bytes scan_graph_create allocates for an in-memory
  * graph of n vertices and nnz arcs under opts (NULL = defaults): row offsets,
  * neighbour ids (and their degree-ranked copy when opts->hub_ranked is set and
- * n > 2^19), the oriented edge list with the degrees of both ends of each
+ * n > 2^19) with every 32nd id sampled, the oriented edge list with the degrees of both ends of each
  * edge, its worklist and edge states, per-vertex
  * state and output staging, plus 1 MiB for small tables.  A graph created with
  * device_budget_bytes below this value takes the partition-based path. */

@@ -43,7 +43,7 @@ namespace {
 
 void release(scan_graph* g) {
   part_release(g);
-  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_edges, g->d_edeg, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
+  void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_hsamp, g->d_edges, g->d_edeg, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -97,6 +97,7 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
   A.edges = g->d_edges;
   A.wtab = g->d_wtab;
   A.edeg = g->d_edeg;
+  A.hsamp = g->d_hsamp;
   A.state = R.state;
   A.lower = R.lower;
   A.upper = R.upper;
@@ -184,6 +185,7 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 16 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
                4 * (uint64_t)g->wtab_entries;
   if (g->d_hci) b += 4 * (nnz + kColPad);
+  if (g->d_hsamp) b += 4 * (uint64_t)sample_lines((int64_t)nnz);
   b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
   if (g->d_out_labels) b += 5 * n;
   if (g->d_counts) b += 4 * nnz;
@@ -235,6 +237,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   A.hci = g->d_hci ? g->d_hci : g->d_ci;
   A.edges = g->d_edges;
   A.wtab = g->d_wtab;
+  A.hsamp = g->d_hsamp;
   A.counts = d_counts_arc;
   A.edge_counts = d_counts_edge;
   A.stats = g->d_stats;
@@ -376,6 +379,10 @@ int scan_graph_create(int32_t n, int64_t nnz, const int64_t* row_ptr, const int3
          "copy windows");
     CTRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
     g->wtab_entries = (int64_t)wtab.size();
+    // the first id of every 128-byte line of those rows
+    CTRY(dalloc(&g->d_hsamp, sample_lines(nnz)), "hipMalloc line samples");
+    launch_line_samples(g->stream, sample_lines(nnz), g->d_hci ? g->d_hci : g->d_ci, g->d_hsamp);
+    CTRY(hipGetLastError(), "line samples");
   }
   for (int k = 0; k <= kNumBuckets; ++k) g->bucket_off[k] = lay.bucket_off[k];
   g->m = lay.bucket_off[kNumBuckets];

@@ -64,6 +64,7 @@ struct scan_graph {
   int64_t* d_rp = nullptr;
   int32_t* d_ci = nullptr;
   int32_t* d_hci = nullptr;  // rows renamed by degree rank (LDS-hash kernel), or null
+  int32_t* d_hsamp = nullptr;  // first id of every 128-byte line of the rows the LDS-hash kernel reads
   int2* d_edges = nullptr;
   HubJob* d_jobs = nullptr;
   int64_t hub_jobs = 0;

@@ -949,7 +949,31 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
           if (q_st[tid] == 1 && q_next[tid] < hi) {
             const int32_t* Arow = A.hci + q_bu[tid];
             int32_t lo = q_pos[tid], hi2 = q_du[tid];
-            if (hi != INT_MAX) {
+            if (hi != INT_MAX && A.hsamp) {
+              // The part ends at the first 128-byte line past the survivor's
+              // position whose first element is >= hi, found in the line
+              // samples (an array of nnz/32 ids, read through the caches)
+              // rather than in the row itself, whose lines would be fetched
+              // here and again, after eviction, by the chunks.  The chunks
+              // then also read up to 31 elements of the part's last line that
+              // are >= hi, and skip them by value.
+              const int64_t bu = q_bu[tid];
+              const int64_t kb = (bu + hi2 - 1) >> 5;  // the row's last line
+              // lines in (a0, a] start below hi; line b starts at or above it
+              // (b = kb + 1: none does), galloping from the position's line a0
+              int64_t a = (bu + lo) >> 5, step = 1;
+              while (a + step <= kb && A.hsamp[a + step] < hi) {
+                a += step;
+                step *= 2;
+              }
+              int64_t b = (a + step <= kb) ? a + step : kb + 1;
+              while (b - a > 1) {
+                const int64_t mid = (a + b) >> 1;
+                if (A.hsamp[mid] < hi) a = mid;
+                else b = mid;
+              }
+              q_end[tid] = (b <= kb) ? (int32_t)((b << 5) - bu) : hi2;
+            } else if (hi != INT_MAX) {
               // first element >= hi, found by galloping from the survivor's
               // position (Arow[lo] < hi): the probes fall on lines of this
               // window's part, which the chunks read next, and at most one past it
@@ -1063,13 +1087,14 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
             P += kStep;
             const int32_t left = ce - p - sub;  // this lane's elements from here on
             int32_t x[kHubUnroll];
+            uint32_t step_seen = 0;  // elements of this window's part (below hi)
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               x[j] = (j * kHubGroup < left) ? xn[j] : kHubNone;
               xn[j] = P[j * kHubGroup];
+              step_seen += ((uint32_t)x[j] < (uint32_t)hi) ? 1u : 0u;  // kHubNone is above every id
             }
             uint32_t step_hits = 0;
-            const uint32_t step_seen = (uint32_t)min(max((left + kHubGroup - 1) / kHubGroup, 0), kHubUnroll);
             if constexpr (kKind == 2) {
               // first buckets only; the second one (and beyond) just for
               // elements whose first bucket is full without them
@@ -1213,6 +1238,12 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
   const unsigned long long splits = wave_sum(n_split);
   if ((tid & 63) == 0 && splits) atomicAdd(A.stats + ST_GROUP_SPLIT, splits);
   flush_stats(A, MODE, n_eval, n_bound, n_probe);
+}
+
+__global__ void k_line_samples(int64_t nlines, const int32_t* rows, int32_t* samp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; k < nlines; k += stride) samp[k] = rows[k << 5];
 }
 
 __global__ void k_edge_degrees(int64_t m, const int64_t* rp, const int2* edges, int2* deg) {
@@ -1819,6 +1850,10 @@ int read16_sink_words() { return 16384 * 256; }
 
 void launch_read16(hipStream_t s, const void* src, int64_t n16, uint32_t* sink) {
   if (n16 > 0) k_read16<<<blocks_for(n16, 256, 16384), 256, 0, s>>>((const uint4*)src, n16, sink);
+}
+
+void launch_line_samples(hipStream_t s, int64_t nlines, const int32_t* rows, int32_t* samp) {
+  if (nlines > 0) k_line_samples<<<blocks_for(nlines, 256, 16384), 256, 0, s>>>(nlines, rows, samp);
 }
 
 void launch_edge_degrees(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, int2* deg) {

@@ -26,10 +26,12 @@ namespace scan {
 
 uint64_t inmemory_footprint(int32_t n, int64_t nnz, bool ranked) {
   const uint64_t m = (uint64_t)nnz / 2;
-  // row_ptr, col_idx (and its ranked copy), oriented edges and their degree
-  // pairs, hub worklist, edge state, per-vertex state + outputs
+  // row_ptr, col_idx (and its ranked copy) with a sample per 32 ids, oriented
+  // edges and their degree pairs, hub worklist, edge state, per-vertex state +
+  // outputs
   const uint64_t cols = (ranked && n > kHubBitmapBits) ? 8ull : 4ull;
-  return 8ull * ((uint64_t)n + 1) + cols * nnz + 16ull * m + 4ull * m + 1ull * m + 22ull * n + (1ull << 20);
+  return 8ull * ((uint64_t)n + 1) + cols * nnz + 4ull * (uint64_t)sample_lines(nnz) + 16ull * m + 4ull * m +
+         1ull * m + 22ull * n + (1ull << 20);
 }
 
 namespace {

@@ -112,6 +112,8 @@ struct EdgeArgs {
   const int2* edges;  // oriented: x = smaller side (deg, id), y = larger side
   const uint32_t* wtab;  // LDS-hash windows of the jobs' larger sides (HubJob::wbeg)
   const int2* edeg;   // degrees of both sides per oriented edge (null: read from rp)
+  const int32_t* hsamp;  // hsamp[k] = hci[32 k], the first id of every 128-byte line of hci
+                         // (null: the LDS-hash kernel searches the rows themselves)
   int64_t e_begin, e_end;
   uint8_t* state;     // per oriented edge
   int32_t* lower;     // confirmed |N_eps| lower bound (starts at 1)
@@ -255,6 +257,12 @@ void launch_batch_edge_offsets(hipStream_t s, int32_t G, const int64_t* vtx_off,
                                const int64_t* bucket_off_host, int64_t* eoff);
 // Blocks of the persistent kernel that fit on the device at once.
 int batch_grid_blocks();
+
+// Lines of 32 ids (128 bytes) that hold nnz ids.
+inline int64_t sample_lines(int64_t nnz) { return (nnz + 31) >> 5; }
+
+// samp[k] = rows[32 k] for k < nlines (rows holds at least 32 (nlines - 1) + 1 ids).
+void launch_line_samples(hipStream_t s, int64_t nlines, const int32_t* rows, int32_t* samp);
 
 // deg[e] = (degree of edges[e].x, degree of edges[e].y) for m oriented edges.
 void launch_edge_degrees(hipStream_t s, int64_t m, const int64_t* rp, const int2* edges, int2* deg);

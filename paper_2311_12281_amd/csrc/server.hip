@@ -497,6 +497,10 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
         (void)hipFree(g->d_hci);
         g->d_hci = nullptr;
       }
+      if (g->d_hsamp) {  // samples of the rows the counting run read
+        (void)hipFree(g->d_hsamp);
+        g->d_hsamp = nullptr;
+      }
       const uint64_t now = graph_device_bytes(g) + 12ull * (uint64_t)g->m;
       std::lock_guard<std::mutex> lk(S->mu);
       S->resident_bytes -= held;
