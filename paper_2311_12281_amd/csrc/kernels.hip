@@ -1076,15 +1076,17 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
           // survivor's running totals itself, so no step needs a reduction
           // across the group.
           uint32_t my_hits = 0, my_seen = 0;
-          // elements of the next step are loaded while this one is probed;
-          // loads may run up to two steps past the chunk (col_idx is padded),
-          // values at or beyond ce are ignored
+          // elements of the next step are loaded while this one is probed
+          // (the last step loads its own elements again, from lines already
+          // fetched, rather than the next ones past the chunk); loads may run
+          // up to one step past the chunk (col_idx is padded), values at or
+          // beyond ce are ignored
           const int32_t* P = Arow + cs + sub;
           int32_t xn[kHubUnroll];
 #pragma unroll
           for (int j = 0; j < kHubUnroll; ++j) xn[j] = P[j * kHubGroup];
           for (int32_t p = cs; p < ce; p += kStep) {
-            P += kStep;
+            P = (p + kStep < ce) ? P + kStep : P;
             const int32_t left = ce - p - sub;  // this lane's elements from here on
             int32_t x[kHubUnroll];
             uint32_t step_seen = 0;  // elements of this window's part (below hi)
