@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-eps10", action="store_true",
+                    help="skip the eps=1/10 timing (profiler runs: only the headline eps launch the kernels)")
     ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched", "sweep"])
     ap.add_argument("--cl-n", type=int, default=50_000_000, help="partitioned: Chung-Lu vertices")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="partitioned: device budget")
@@ -71,12 +73,19 @@ def main():
     ap.add_argument("--serve-plain-seconds", type=float, default=10.0,
                     help="serving: arrivals of the plain comparison (bounded run)")
     ap.add_argument("--batch-count", type=int, default=10000)
+    ap.add_argument("--batch-trace", action="store_true",
+                    help="batched: default launch parameters, only the timed replays (for a kernel trace)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy calibration")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="DIR",
                     help="print the HBM traffic summary of rocprofv3 --pmc runs of this bench (FETCH_SIZE, "
                          "WRITE_SIZE, read requests by size, DRAM requests)")
     ap.add_argument("--pmc-kernel", default="k_hub<0>")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="print a markdown table of the rocprofv3 --stats kernel summary under DIR and exit")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats)
+        return
     if args.summarize_pmc:
         return summarize_pmc(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -175,32 +184,42 @@ def main():
     dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
     traffic = _traffic_from_profile(dom_kernel)
     # every bucket's kernel against the same roofline, and the whole cores pass
+    # (the intersection bytes above, and beside them the same plus the classification stream:
+    # 8 bytes of endpoints, 8 of degrees and 1 of edge state for every edge of the bucket)
     buckets = []
     for b in range(nb):
         ms_l = ms_b[b] / launches
         alg_l = bytes_b[b] / launches
+        eb = int(stats[0]["bucket_edges"][b])
+        cls_l = alg_l + 17.0 * eb
         buckets.append({"bucket": b, "launch_ms": float(ms_l), "alg_bytes_per_launch": float(alg_l),
                         "achieved_GBs": float(alg_l / (ms_l * 1e-3) / 1e9) if ms_l > 0 else 0.0,
                         "frac": float(alg_l / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS) if ms_l > 0 else 0.0,
-                        "edges": int(stats[0]["bucket_edges"][b])})
+                        "edges": eb,
+                        "edges_per_s": float(eb / (ms_l * 1e-3)) if ms_l > 0 else 0.0,
+                        "bytes_incl_classify_per_launch": float(cls_l),
+                        "frac_incl_classify": float(cls_l / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS) if ms_l > 0 else 0.0})
     cores_ms = sum(st["ms_phase"]["cores"] for st in stats) / launches
     cores_alg = float(bytes_b.sum() / launches)
     cores_pass = {"launch_ms": cores_ms, "alg_bytes_per_launch": cores_alg,
                   "frac": cores_alg / (cores_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if cores_ms > 0 else 0.0}
     # the non-degenerate point of this graph (eps = 1/10 has cores and clusters), timed beside the step
     dl10, dr10 = S.scan_device_alloc(4 * n), S.scan_device_alloc(n)
-    for _ in range(2):
-        G.run_device(1, 10, MU, dl10, dr10)
-    t10 = []
-    st10 = None
-    for _ in range(max(3, args.steps // 2)):
-        t = time.perf_counter()
-        G.run_device(1, 10, MU, dl10, dr10)
-        t10.append(time.perf_counter() - t)
-        st10 = G.stats()
-    eps10 = {"eps": "1/10", "ms_wall": float(np.median(t10) * 1e3), "ms_device": st10["ms_total"],
-             "ms_phase": st10["ms_phase"], "edges_per_s": float(m / np.median(t10))}
-    log(f"eps=1/10 (not in the headline step): {eps10['ms_wall']:.1f} ms, {eps10['edges_per_s'] / 1e9:.2f} G edges/s")
+    eps10 = None
+    if not args.no_eps10:
+        for _ in range(2):
+            G.run_device(1, 10, MU, dl10, dr10)
+        t10 = []
+        st10 = None
+        for _ in range(max(3, args.steps // 2)):
+            t = time.perf_counter()
+            G.run_device(1, 10, MU, dl10, dr10)
+            t10.append(time.perf_counter() - t)
+            st10 = G.stats()
+        eps10 = {"eps": "1/10", "ms_wall": float(np.median(t10) * 1e3), "ms_device": st10["ms_total"],
+                 "ms_phase": st10["ms_phase"], "edges_per_s": float(m / np.median(t10))}
+        log(f"eps=1/10 (not in the headline step): {eps10['ms_wall']:.1f} ms, "
+            f"{eps10['edges_per_s'] / 1e9:.2f} G edges/s")
 
     # PCIe-inclusive rate (host outputs), reported beside the value
     t = time.perf_counter()
@@ -409,10 +428,10 @@ def summarize_pmc(args):
 Commands (from the repository root on the MI355X host, each its own run):
 
 ```
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
-rocprofv3 --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_rdreq -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
-rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_dram -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
+rocprofv3 --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_rdreq -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
+rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_dram -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
 {cmd}
 ```
 
@@ -438,6 +457,71 @@ those that went to DRAM:
 - kernel_sources_sha256: `{_kernel_source_hash()}`
 - traffic_bytes_per_launch: {traffic:.0f}
 """)
+    bt = _bucket_traffic(rows, sf, sw)
+    print("Every cores-pass kernel, by degree bucket (scaled FETCH_SIZE and WRITE_SIZE per dispatch, GB;")
+    print("dispatches are those of the FETCH and WRITE runs together):\n")
+    print("| bucket | kernel | dispatches | read GB | written GB |")
+    print("|---|---|---|---|---|")
+    kn = ["k_group<0, 4>", "k_group<0, 8>", "k_group<0, 16>", "k_group<0, 32>", "k_group<0, 64, staged>",
+          "k_group<0, 64, staged>", "k_hub<0>"]
+    for b in range(7):
+        nd, f, w = bt.get(b, (0, None, None))
+        print(f"| {b} | `{kn[b]}` | {nd} | {'-' if f is None else f'{f / 1e9:.3f}'} | "
+              f"{'-' if w is None else f'{w / 1e9:.3f}'} |")
+
+
+def _short_kernel(name):
+    """Kernel name without namespaces, argument list and the default template arguments."""
+    nm = name
+    for pre in ("void ", "(anonymous namespace)::", "scan::"):
+        nm = nm.replace(pre, "")
+    nm = nm.split("(")[0].replace(", false>", ">").replace(", true>", ", staged>")
+    return nm.strip()
+
+
+def summarize_stats(d):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (csv output) under d."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        sys.exit(f"no kernel_stats.csv under {d}")
+    rows = {}
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = _short_kernel(r["Name"])
+                c, t = rows.get(k, (0, 0.0))
+                rows[k] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
+    total = sum(t for _, t in rows.values())
+    print("| kernel | calls | total ms | average ms | % |")
+    print("|---|---|---|---|---|")
+    for k, (c, t) in sorted(rows.items(), key=lambda kv: -kv[1][1]):
+        if t / total < 0.001:
+            continue
+        print(f"| `{k}` | {c} | {t / 1e6:.2f} | {t / c / 1e6:.3f} | {100 * t / total:.2f} |")
+
+
+def _bucket_traffic(rows, sf, sw):
+    """Scaled FETCH/WRITE bytes per dispatch of every cores-pass kernel, by degree bucket.  Buckets 4
+    and 5 share one kernel (lanes 64, staged) and are told apart by launch order (4 before 5)."""
+    names = [("k_group<0, 4,", (0,)), ("k_group<0, 8,", (1,)), ("k_group<0, 16,", (2,)),
+             ("k_group<0, 32,", (3,)), ("k_group<0, 64, true", (4, 5)), ("k_hub<0>", (6,))]
+    out = {}
+    for key, bks in names:
+        per = {}
+        for did, nm, c, v in rows:
+            if key in nm.replace("(scan::Mode)", "") and c in ("FETCH_SIZE", "WRITE_SIZE"):
+                per.setdefault(int(did), {}).setdefault(c, 0.0)
+                per[int(did)][c] += v
+        ids = sorted(per)
+        for j, b in enumerate(bks):
+            mine = [per[i] for i in ids[j::len(bks)]]
+            f = [x["FETCH_SIZE"] for x in mine if "FETCH_SIZE" in x]
+            w = [x["WRITE_SIZE"] for x in mine if "WRITE_SIZE" in x]
+            out[b] = (len(mine), sum(f) / len(f) * sf * 1024.0 if f else None,
+                      sum(w) / len(w) * sw * 1024.0 if w else None)
+    return out
 
 
 def _line(metric, value, unit, config, **rest):
@@ -502,7 +586,8 @@ def bench_serving(args):
     slots, memory admission (an upload that does not fit stays on the host
     and its queries take the partition-based path on the fallback thread).
     Plain: one scan_run per query on resident graphs, first come first served,
-    at the same arrivals.  Latency = completion - arrival.  Exactness: the
+    at 0.5x and 0.9x of its own saturation and at the served path's rates.
+    Latency = completion - arrival.  Exactness: the
     stored oracle digests of two queries per graph, and every query of the
     Poisson runs against the same query run alone afterwards."""
     import threading
@@ -637,16 +722,21 @@ def bench_serving(args):
         fallback = {"graph_edges": all_graphs[g_index[gid]].m, "latency_ms": ms}
         log(f"fallback queries: {fallback}")
 
-    # plain: one scan_run per query, resident graphs, same arrival process, bounded count
+    # plain: one scan_run per query on the resident graphs, first come first served, the same
+    # query list; its own saturation (queries back to back), then Poisson arrivals at 0.5x and 0.9x
+    # of that rate and at the served path's rates (where its queue grows).  Each run stops after
+    # --serve-plain-seconds: latencies are those of the queries completed by then, and `backlog`
+    # counts the queries that had arrived but were still waiting.
     plain_graphs = {gid: S.Graph.from_csr(all_graphs[g_index[gid]]) for gid in res_gids}
-    for frac in (0.5, 0.9):
-        qps = frac * sat
-        cnt = min(nq, max(100, int(qps * args.serve_plain_seconds)))
-        arr = np.cumsum(np.random.default_rng(int(qps)).exponential(1.0 / qps, size=cnt))
+
+    def run_plain(qps, cnt):
+        arr = np.cumsum(np.random.default_rng(int(qps)).exponential(1.0 / qps, size=cnt)) if qps else np.zeros(cnt)
         lat = []
         edges = 0.0
         start = time.perf_counter()
         for k in range(cnt):
+            if time.perf_counter() - start > args.serve_plain_seconds:
+                break
             d = start + arr[k] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
@@ -656,11 +746,20 @@ def bench_serving(args):
             lat.append((time.perf_counter() - start - arr[k]) * 1e3)
             edges += all_graphs[g_index[gid]].m
         wall = time.perf_counter() - start
-        o = out[f"{frac}x"]
-        o.update({"plain_queries": cnt, "plain_p50_ms": float(np.percentile(lat, 50)),
-                  "plain_p99_ms": float(np.percentile(lat, 99)), "plain_edges_per_s": edges / wall})
-        log(f"plain {frac}x: p50 {o['plain_p50_ms']:.1f} ms p99 {o['plain_p99_ms']:.1f} ms "
-            f"{o['plain_edges_per_s'] / 1e9:.2f} G edges/s over {cnt} queries")
+        backlog = int(np.searchsorted(arr, wall, side="right")) - len(lat)
+        return np.array(lat), edges, wall, backlog
+
+    lat, edges, wall, _ = run_plain(0.0, nq)
+    plain_sat = len(lat) / wall
+    plain = {"saturation_qps": plain_sat, "saturation_edges_per_s": edges / wall, "saturation_queries": len(lat)}
+    log(f"plain saturation: {plain_sat:.0f} queries/s, {edges / wall / 1e9:.2f} G edges/s")
+    for frac in (0.5, 0.9):
+        for label, qps in ((f"own_{frac}x", frac * plain_sat), (f"served_rate_{frac}x", frac * sat)):
+            lat, edges, wall, backlog = run_plain(qps, nq)
+            plain[label] = {"qps": qps, "queries": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+                            "p99_ms": float(np.percentile(lat, 99)), "edges_per_s": edges / wall,
+                            "backlog": backlog}
+            log(f"plain {label}: {plain[label]}")
     for G in plain_graphs.values():
         G.close()
 
@@ -695,7 +794,7 @@ def bench_serving(args):
           {"workload": f"serving_rmat{len(graphs)}+{len(uploads)}_s16-23_ef8-32", "resident_graphs": len(graphs),
            "uploads": len(uploads), "queries": nq, "slots": nslots, "budget_bytes": budget},
           saturation_edges_per_s=sat_edges / sat_s, add_graphs_s=add_s, oracle_digests_exact=oracle_ok,
-          alone_run_exact=alone_ok, fallback=fallback, poisson=out)
+          alone_run_exact=alone_ok, fallback=fallback, poisson=out, plain=plain)
 
 
 def bench_batched(args):
@@ -719,7 +818,7 @@ def bench_batched(args):
     log(f"{len(graphs)} graphs, {sum(g.n for g in graphs)} vertices, {m} edges, generated in "
         f"{time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
-    B = S.Batch(graphs, eps, mus, autotune=True)
+    B = S.Batch(graphs, eps, mus, autotune=not args.batch_trace)
     create_s = time.perf_counter() - t
     lanes, tile = B.config()
     log(f"batch created and autotuned in {create_s:.1f}s: lanes {lanes}, {tile} edges per tile")
@@ -734,6 +833,12 @@ def bench_batched(args):
     batch_ms = float(np.median(dev_ms))
     log(f"batched: {batch_ms:.1f} ms device per run ({m / batch_ms / 1e6:.2f} G edges/s), "
         f"{wall_s * 1e3:.1f} ms wall with host outputs")
+    if args.batch_trace:
+        B.close()
+        _line("edges/s (|E|/solve), batched, trace run", m / (batch_ms * 1e-3), "edges/s",
+              {"workload": f"planted_batch_{len(graphs)}", "graphs": len(graphs), "m": m},
+              replays=args.warmup + args.steps, ms_per_batch_device=batch_ms, lanes=lanes, tile_edges=tile)
+        return
     ls, rs = B.split(labels), B.split(roles)
     gold_path = os.path.join(ROOT, "tests", "golden", "planted_batch_10000_seed4.json")
     if args.batch_count == 10000 and os.path.exists(gold_path):
