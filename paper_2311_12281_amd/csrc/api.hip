@@ -182,7 +182,7 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   if (g->partitioned) return 0;
   const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, m = (uint64_t)g->m;
   const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
-  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 16 * m + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
+  uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + (g->d_edeg ? 8 * m : 0) + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
                4 * (uint64_t)g->wtab_entries;
   if (g->d_hci) b += 4 * (nnz + kColPad);
   if (g->d_hsamp) b += 4 * (uint64_t)sample_lines((int64_t)nnz);

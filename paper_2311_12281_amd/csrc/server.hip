@@ -491,8 +491,9 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
       }
     }
     if (rc == SCAN_OK) {
-      // queries never intersect again: the rows renamed by degree rank, used
-      // only by the counting run, are released
+      // queries never intersect again: the rows renamed by degree rank and
+      // the other inputs of the intersections, used only by the counting run,
+      // are released
       if (g->d_hci) {
         (void)hipFree(g->d_hci);
         g->d_hci = nullptr;
@@ -500,6 +501,10 @@ int scan_server_add_graph(scan_server* S, int32_t n, int64_t nnz, const int64_t*
       if (g->d_hsamp) {  // samples of the rows the counting run read
         (void)hipFree(g->d_hsamp);
         g->d_hsamp = nullptr;
+      }
+      if (g->d_edeg) {  // degree pairs (the closed-size products replace them)
+        (void)hipFree(g->d_edeg);
+        g->d_edeg = nullptr;
       }
       const uint64_t now = graph_device_bytes(g) + 12ull * (uint64_t)g->m;
       std::lock_guard<std::mutex> lk(S->mu);
