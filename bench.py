@@ -26,7 +26,10 @@ Other workloads (their own JSON line, not the default):
                           served (cached counts, continuous batching) vs
                           plain per-query scan_run: p50/p99 latency, edges/s;
   --workload batched      many planted-partition graphs in one captured
-                          launch vs one scan_run per graph.
+                          launch vs one scan_run per graph;
+  --workload sweep        R-MAT scale 22 over eps at mu = 6 and over mu at eps = 1/2;
+  --workload planted      planted partition n = 10,000 with the oracle at
+                          one thread and at all threads.
 """
 from __future__ import annotations
 
@@ -62,7 +65,8 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-eps10", action="store_true",
                     help="skip the eps=1/10 timing (profiler runs: only the headline eps launch the kernels)")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "partitioned", "serving", "batched", "sweep"])
+    ap.add_argument("--workload", default="rmat",
+                    choices=["rmat", "planted", "partitioned", "serving", "batched", "sweep"])
     ap.add_argument("--cl-n", type=int, default=50_000_000, help="partitioned: Chung-Lu vertices")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="partitioned: device budget")
     ap.add_argument("--serve-graphs", type=int, default=64, help="serving: resident R-MAT graphs")
@@ -102,6 +106,8 @@ def main():
         return bench_batched(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "planted":
+        return bench_planted(args)
 
     import graphgen as gg
     import paper_2311_12281_amd as S
@@ -872,6 +878,61 @@ def bench_batched(args):
           ms_per_batch_device=batch_ms, ms_per_batch_wall=wall_s * 1e3, plain_edges_per_s=m / plain_s,
           plain_ms=plain_s * 1e3, identical_to_plain=same, exactness=exact, autotuned_lanes=lanes,
           tile_edges=tile, create_s=create_s)
+
+
+def bench_planted(args):
+    """Planted partition n = 10,000 (50 blocks, p_in 0.15, p_out 0.0005, seed 1) at eps = 1/2,
+    1/5, 1/10 and mu = 5: device time per solve (median of --steps after --warmup) and the oracle
+    on one host thread and on all of them (closed counts of every edge plus clustering), each
+    result compared with the oracle's."""
+    import graphgen as gg
+    import oracle
+    import paper_2311_12281_amd as S
+
+    g = gg.planted(10000, 50, 0.15, 0.0005, 1)
+    n, m = g.n, g.m
+    threads = oracle.max_threads()
+    points = []
+    exact = True
+    with S.Graph.from_csr(g, timing=True) as G:
+        dl, dr = S.scan_device_alloc(4 * n), S.scan_device_alloc(n)
+        for p, q in ((1, 2), (1, 5), (1, 10)):
+            for _ in range(args.warmup):
+                G.run_device(p, q, MU, dl, dr)
+            wall, dev = [], []
+            for _ in range(args.steps):
+                t = time.perf_counter()
+                G.run_device(p, q, MU, dl, dr)
+                wall.append(time.perf_counter() - t)
+                dev.append(G.stats()["ms_total"])
+            gl = np.empty(n, np.int32)
+            gr = np.empty(n, np.uint8)
+            S.scan_memcpy_d2h(gl, dl, 4 * n)
+            S.scan_memcpy_d2h(gr, dr, n)
+            cpu = {}
+            for T in (1, threads):
+                ts = []
+                for _ in range(3):
+                    t = time.perf_counter()
+                    ol, orr = oracle.scan(g, p, q, MU, threads=T)
+                    ts.append(time.perf_counter() - t)
+                cpu[T] = float(np.median(ts))
+            ok = bool(np.array_equal(gl, ol) and np.array_equal(gr, orr))
+            exact = exact and ok
+            pt = {"eps": f"{p}/{q}", "mu": MU, "ms_wall": float(np.median(wall) * 1e3),
+                  "ms_device": float(np.median(dev)), "edges_per_s": float(m / np.median(wall)),
+                  "oracle_t1_edges_per_s": m / cpu[1], "oracle_tall_edges_per_s": m / cpu[threads],
+                  "cores": int((orr == 1).sum()), "exact_match": ok}
+            points.append(pt)
+            log(f"planted n={n} m={m}: {pt}")
+        S.scan_device_free(dl)
+        S.scan_device_free(dr)
+    _line("edges/s (|E|/solve) exact-match, small planted graph", float(np.median([p["edges_per_s"] for p in points])),
+          "edges/s", {"workload": "planted_n10000_b50_seed1", "n": n, "m": m},
+          exact_match=exact, points=points,
+          cpu_baseline={"kind": "oracle", "cores": threads, "cpu_model": _cpu_model(),
+                        "sample": "the same graph and eps, closed counts of every edge plus clustering, "
+                                  "median of 3 runs at 1 thread and at all threads"})
 
 
 def bench_sweep(args):
