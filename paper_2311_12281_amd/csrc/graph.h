@@ -17,14 +17,18 @@ using namespace scan;
 // one pair's edges (grouped by degree bucket) small enough for the device
 // edge buffer.
 struct PartChunk {
-  int32_t bi, bj;                          // block pair, bi <= bj
+  int32_t bi, bj;                          // block bi with unit bj of a later block (-1: edges inside bi)
   int64_t begin, end;                      // range of the pinned edge array
   int64_t bucket_off[kNumBuckets + 1];     // bucket sub-ranges, clipped to [begin, end)
   int64_t job_off = 0, job_cnt = 0;        // LDS-hash jobs of the last bucket (chunk-relative edges)
 };
 
 struct PartPlan {
-  std::vector<int32_t> block_lo;  // K+1 vertex boundaries
+  std::vector<int32_t> block_lo;  // K+1 vertex boundaries of the blocks
+  std::vector<int32_t> unit_lo;   // U+1 vertex boundaries of the units (a block is upb units)
+  int32_t upb = 1;                // units per block
+  int32_t nslots = 1;             // device slots for units (2: the next unit uploads while one is read)
+  int64_t jcap = 0;               // ints per unit slot (slots follow the block's half of the row buffer)
   std::vector<int64_t> h_rp;      // host copy of row_ptr
   std::vector<PartChunk> chunks;
   int32_t* h_ci = nullptr;        // pinned copy of col_idx
@@ -43,8 +47,10 @@ struct PartPlan {
   uint32_t* d_wtab = nullptr;     // their windows
   int32_t* d_worklist = nullptr;  // one slot per edge of a chunk
   unsigned long long* d_jobctr = nullptr;
-  hipStream_t copy = nullptr;     // upload stream (default priority)
+  hipStream_t copy = nullptr;     // upload stream of edges and states (default priority)
   hipEvent_t up[2] = {}, done[2] = {};
+  hipStream_t rowcopy = nullptr;  // upload stream of unit rows (default priority)
+  hipEvent_t rready[2] = {}, rfree[2] = {};  // per unit slot: rows uploaded / last reader done
   uint64_t h2d_bytes = 0;         // bytes sent to the device by the last call
   int64_t chunks_streamed = 0;    // chunks sent by the last call (passes that skip chunks send fewer)
 };

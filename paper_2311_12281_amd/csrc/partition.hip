@@ -62,8 +62,11 @@ void part_release(scan_graph* g) {
   for (int b = 0; b < 2; ++b) {
     if (P.up[b]) (void)hipEventDestroy(P.up[b]);
     if (P.done[b]) (void)hipEventDestroy(P.done[b]);
+    if (P.rready[b]) (void)hipEventDestroy(P.rready[b]);
+    if (P.rfree[b]) (void)hipEventDestroy(P.rfree[b]);
   }
   if (P.copy) (void)hipStreamDestroy(P.copy);
+  if (P.rowcopy) (void)hipStreamDestroy(P.rowcopy);
   P = PartPlan();
 }
 
@@ -107,40 +110,63 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
   int64_t chunk_cap = (int64_t)((rest / 4) / kEdgeBytes);
   if (chunk_cap > m) chunk_cap = m;
   if (chunk_cap < 1) chunk_cap = 1;
-  const int64_t row_cap = (int64_t)((rest - (uint64_t)chunk_cap * kEdgeBytes) / 4);  // two blocks
-  const int64_t blk_cap = row_cap / 2;
+  // The row buffer holds a block (its first half) and units of later blocks
+  // (the second half).  A block is two units of at most a quarter of the
+  // buffer, so the second half has two unit slots and the next unit's rows
+  // are uploaded while the current one is read; when the longest row does not
+  // fit a quarter, a block is one unit and the second half a single slot.
+  const int64_t row_cap = (int64_t)((rest - (uint64_t)chunk_cap * kEdgeBytes) / 4);
   int64_t maxdeg = 0;
   for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp[v + 1] - rp[v]);
-  if (maxdeg > blk_cap || blk_cap < 1)
+  const bool two = row_cap / 4 >= 1 && maxdeg <= row_cap / 4;
+  P.upb = two ? 2 : 1;
+  P.nslots = two ? 2 : 1;
+  P.jcap = row_cap / 2 / P.nslots;
+  const int64_t ucap = P.jcap;
+  if (maxdeg > ucap || ucap < 1)
     return fail(SCAN_E_NOMEM, "budget too small: a row of %lld neighbours does not fit a block of %lld",
-                (long long)maxdeg, (long long)blk_cap);
-  // blocks: contiguous vertex ranges with at most blk_cap arcs
-  P.block_lo.clear();
-  P.block_lo.push_back(0);
+                (long long)maxdeg, (long long)(row_cap / 2));
+  // units: contiguous vertex ranges with at most ucap arcs; blocks: runs of upb units
+  P.unit_lo.clear();
+  P.unit_lo.push_back(0);
   for (int32_t v = 0; v < n; ++v) {
-    const int64_t start = rp[P.block_lo.back()];
-    if (rp[v + 1] - start > blk_cap) P.block_lo.push_back(v);
+    const int64_t start = rp[P.unit_lo.back()];
+    if (rp[v + 1] - start > ucap) P.unit_lo.push_back(v);
   }
+  P.unit_lo.push_back(n);
+  const int32_t U = (int32_t)P.unit_lo.size() - 1;
+  const int32_t K = (U + P.upb - 1) / P.upb;
+  P.block_lo.clear();
+  for (int32_t b = 0; b < K; ++b) P.block_lo.push_back(P.unit_lo[(size_t)b * P.upb]);
   P.block_lo.push_back(n);
-  const int32_t K = (int32_t)P.block_lo.size() - 1;
   P.h_rp.assign(rp, rp + n + 1);
   auto block_of = [&](int32_t x) {
     return (int32_t)(std::upper_bound(P.block_lo.begin(), P.block_lo.end(), x) - P.block_lo.begin()) - 1;
   };
-  auto pair_index = [&](int32_t i, int32_t j) { return (int64_t)i * K - (int64_t)i * (i - 1) / 2 + (j - i); };
-  const int64_t npairs = (int64_t)K * (K + 1) / 2;
+  auto unit_of = [&](int32_t x) {
+    return (int32_t)(std::upper_bound(P.unit_lo.begin(), P.unit_lo.end(), x) - P.unit_lo.begin()) - 1;
+  };
+  // pairs of block i: its own edges, then one per unit of a later block
+  const int32_t upb = P.upb;
+  std::vector<int64_t> pair_base((size_t)K + 1, 0);
+  for (int32_t i = 0; i < K; ++i) pair_base[(size_t)i + 1] = pair_base[(size_t)i] + 1 + std::max(0, U - upb * (i + 1));
+  auto pair_local = [&](int32_t i, int32_t j) { return j < 0 ? 0 : 1 + (j - upb * (i + 1)); };
+  auto pair_index = [&](int32_t i, int32_t j) { return pair_base[(size_t)i] + pair_local(i, j); };
+  const int64_t npairs = pair_base[(size_t)K];
   const int NB = kNumBuckets;
   std::vector<int64_t> cnt((size_t)(npairs * NB), 0);
   const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   // an edge {u, v} is listed from the row of its endpoint in the lower block
-  // (the smaller id inside one block); it is stored as (smaller, larger) by
-  // (degree, id) and bucketed by the smaller degree
+  // (the smaller id inside one block), in the pair of that block with the
+  // other endpoint's unit (or the block's own pair); it is stored as
+  // (smaller, larger) by (degree, id) and bucketed by the smaller degree
   auto for_edges_of_block = [&](int32_t i, auto&& fn) {
     for (int32_t u = P.block_lo[i]; u < P.block_lo[i + 1]; ++u) {
       for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
         const int32_t v = ci[k];
-        const int32_t j = block_of(v);
-        if (j < i || (j == i && v < u)) continue;
+        const int32_t bv = block_of(v);
+        if (bv < i || (bv == i && v < u)) continue;
+        const int32_t j = bv == i ? -1 : unit_of(v);
         const int64_t du = rp[u + 1] - rp[u], dv = rp[v + 1] - rp[v];
         const bool u_small = du < dv || (du == dv && u < v);
         fn(j, u_small ? u : v, u_small ? v : u, u_small ? part_bucket(du, dv) : part_bucket(dv, du));
@@ -171,12 +197,13 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
       th.emplace_back([&, t]() {
         std::vector<int64_t> cur((size_t)NB);
         for (int32_t i = t; i < K; i += nth) {
-          // cursors of the pairs (i, j >= i): written only by this thread
-          std::vector<int64_t> pc((size_t)((K - i) * NB));
-          for (int32_t j = i; j < K; ++j)
-            for (int b = 0; b < NB; ++b) pc[(size_t)((j - i) * NB + b)] = off[(size_t)(pair_index(i, j) * NB + b)];
+          // cursors of the pairs of block i: written only by this thread
+          const int64_t np = pair_base[(size_t)i + 1] - pair_base[(size_t)i];
+          std::vector<int64_t> pc((size_t)(np * NB));
+          for (int64_t q = 0; q < np; ++q)
+            for (int b = 0; b < NB; ++b) pc[(size_t)(q * NB + b)] = off[(size_t)((pair_base[(size_t)i] + q) * NB + b)];
           for_edges_of_block(i, [&](int32_t j, int32_t su, int32_t lv, int b) {
-            P.h_edges[pc[(size_t)((j - i) * NB + b)]++] = make_int2(su, lv);
+            P.h_edges[pc[(size_t)(pair_local(i, j) * NB + b)]++] = make_int2(su, lv);
           });
         }
       });
@@ -196,9 +223,13 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
       });
     for (auto& x : th) x.join();
   }
-  // chunks: runs of one pair of at most chunk_cap edges
+  // chunks: runs of one pair of at most chunk_cap edges; a block's own pair
+  // first, then its pairs with later units from the last unit down, so that
+  // the last units read are the next block's (their rows are copied on the
+  // device when that block comes up)
   for (int32_t i = 0; i < K; ++i)
-    for (int32_t j = i; j < K; ++j) {
+    for (int32_t j = -1; j == -1 || j >= upb * (i + 1); j = (j < 0 ? U - 1 : j - 1)) {
+      if (j >= U) continue;
       const int64_t pi = pair_index(i, j);
       const int64_t b0 = off[(size_t)(pi * NB)], b1 = off[(size_t)(pi * NB + NB)];
       for (int64_t c0 = b0; c0 < b1; c0 += chunk_cap) {
@@ -266,7 +297,12 @@ int part_create(scan_graph* g, const int64_t* rp, const int32_t* ci, uint64_t bu
       (e = hipEventCreateWithFlags(&P.up[0], hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&P.up[1], hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&P.done[0], hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&P.done[1], hipEventDisableTiming)) != hipSuccess)
+      (e = hipEventCreateWithFlags(&P.done[1], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&P.rowcopy, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.rready[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.rready[1], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.rfree[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&P.rfree[1], hipEventDisableTiming)) != hipSuccess)
     return fail_hip(e, "device buffers");
   if (!jobs.empty() &&
       ((e = hipMemcpy(P.d_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -281,42 +317,105 @@ namespace {
 
 struct Streamer {
   scan_graph* g;
-  hipStream_t s;
-  int32_t li = -1, lj = -1;
-  int64_t len_i = 0;
+  hipStream_t s;  // compute stream
+  int32_t li = -1;   // block whose rows are in the buffer's first half
+  int32_t slot_unit[2] = {-1, -1};  // unit whose rows a slot holds (or is receiving)
+  int32_t last_slot = -1;  // slot read by the previous run of chunks
+  int32_t next_slot = 0;   // slot the next upload goes to
 
-  // Makes the rows of blocks i and j resident and returns the row mapping.
-  hipError_t rows(int32_t i, int32_t j, EdgeArgs& A) {
+  int64_t slot_off(int k) const { return g->part.jcap * (g->part.nslots == 2 ? 2 : 1) + (int64_t)k * g->part.jcap; }
+
+  // Unit j's rows into a slot, on the row stream once the slot's last reader
+  // is done; returns the slot.  A unit already held is not sent again.
+  int load_unit(int32_t j, int avoid, hipError_t& e) {
     PartPlan& P = g->part;
-    const int32_t lo_i = P.block_lo[(size_t)i], hi_i = P.block_lo[(size_t)i + 1];
-    const int32_t lo_j = P.block_lo[(size_t)j], hi_j = P.block_lo[(size_t)j + 1];
+    for (int k = 0; k < P.nslots; ++k)
+      if (slot_unit[k] == j) return k;
+    int k = next_slot;
+    if (k == avoid && P.nslots == 2) k ^= 1;
+    next_slot = (k + 1) % P.nslots;
+    const int32_t lo = P.unit_lo[(size_t)j], hi = P.unit_lo[(size_t)j + 1];
+    const int64_t len = P.h_rp[(size_t)hi] - P.h_rp[(size_t)lo];
+    if (e == hipSuccess) e = hipStreamWaitEvent(P.rowcopy, P.rfree[k], 0);
+    if (e == hipSuccess && len > 0)
+      e = hipMemcpyAsync(P.d_rows + slot_off(k), P.h_ci + P.h_rp[(size_t)lo], sizeof(int32_t) * (size_t)len,
+                         hipMemcpyHostToDevice, P.rowcopy);
+    if (e == hipSuccess) e = hipEventRecord(P.rready[k], P.rowcopy);
+    P.h2d_bytes += 4ull * (uint64_t)len;
+    slot_unit[k] = j;
+    return k;
+  }
+
+  // Called for the first chunk of every run of chunks with the same pair
+  // (i, j), before any of its work is enqueued: makes block i's rows and unit
+  // j's rows resident, sets the row mapping, and starts uploading the unit of
+  // the next run (next_j, -1 if none) into the other slot.
+  hipError_t enter(int32_t i, int32_t j, int32_t next_j, EdgeArgs& A) {
+    PartPlan& P = g->part;
     hipError_t e = hipSuccess;
-    if (i != li) {
-      len_i = P.h_rp[(size_t)hi_i] - P.h_rp[(size_t)lo_i];
-      if (len_i > 0)
-        e = hipMemcpyAsync(P.d_rows, P.h_ci + P.h_rp[(size_t)lo_i], sizeof(int32_t) * (size_t)len_i,
-                           hipMemcpyHostToDevice, s);
-      P.h2d_bytes += 4ull * (uint64_t)len_i;
+    if (last_slot >= 0) e = hipEventRecord(P.rfree[last_slot], s);  // the previous run's reads come first
+    last_slot = -1;
+    const int32_t lo_i = P.block_lo[(size_t)i], hi_i = P.block_lo[(size_t)i + 1];
+    if (e == hipSuccess && i != li) {
+      // block rows on the compute stream (every earlier chunk has read the old
+      // ones), unit by unit: a unit a slot holds is copied on the device
+      const int32_t u_end = std::min<int32_t>((i + 1) * P.upb, (int32_t)P.unit_lo.size() - 1);
+      for (int32_t u = i * P.upb; u < u_end && e == hipSuccess; ++u) {
+        const int64_t b = P.h_rp[(size_t)P.unit_lo[(size_t)u]], len = P.h_rp[(size_t)P.unit_lo[(size_t)u + 1]] - b;
+        const int64_t at = b - P.h_rp[(size_t)lo_i];
+        if (len <= 0) continue;
+        int k = -1;
+        for (int q = 0; q < P.nslots; ++q)
+          if (slot_unit[q] == u) k = q;
+        if (k >= 0) {
+          e = hipMemcpyAsync(P.d_rows + at, P.d_rows + slot_off(k), sizeof(int32_t) * (size_t)len,
+                             hipMemcpyDeviceToDevice, s);
+        } else {
+          e = hipMemcpyAsync(P.d_rows + at, P.h_ci + b, sizeof(int32_t) * (size_t)len, hipMemcpyHostToDevice, s);
+          P.h2d_bytes += 4ull * (uint64_t)len;
+        }
+      }
+      // the slots' next uploads wait for these copies
+      for (int q = 0; q < P.nslots && e == hipSuccess; ++q) e = hipEventRecord(P.rfree[q], s);
       li = i;
-      lj = -1;
-    }
-    if (e == hipSuccess && j != i && j != lj) {
-      const int64_t len_j = P.h_rp[(size_t)hi_j] - P.h_rp[(size_t)lo_j];
-      if (len_j > 0)
-        e = hipMemcpyAsync(P.d_rows + len_i, P.h_ci + P.h_rp[(size_t)lo_j], sizeof(int32_t) * (size_t)len_j,
-                           hipMemcpyHostToDevice, s);
-      P.h2d_bytes += 4ull * (uint64_t)len_j;
-      lj = j;
     }
     A.ci = P.d_rows;
     A.hci = P.d_rows;
     A.a_lo = lo_i;
     A.a_hi = hi_i;
     A.delta_a = P.h_rp[(size_t)lo_i];
-    A.delta_b = P.h_rp[(size_t)lo_j] - len_i;
+    A.delta_b = A.delta_a;
+    if (j >= 0) {
+      const int k = load_unit(j, -1, e);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, P.rready[k], 0);
+      A.delta_b = P.h_rp[(size_t)P.unit_lo[(size_t)j]] - slot_off(k);
+      last_slot = k;
+    }
+    if (next_j >= 0 && next_j != j && P.nslots == 2) (void)load_unit(next_j, last_slot, e);
+    return e;
+  }
+
+  // After the last chunk: the slots' last readers are the chunks enqueued so far.
+  hipError_t finish() {
+    hipError_t e = hipSuccess;
+    if (last_slot >= 0) e = hipEventRecord(g->part.rfree[last_slot], s);
+    last_slot = -1;
     return e;
   }
 };
+
+// The unit of the first run after chunk list[idx]'s run that reads one, in
+// the same block (-1: none; the slots may hold the next block's units, which
+// are copied from them when it comes up).
+int32_t next_unit(const PartPlan& P, const std::vector<int32_t>& list, size_t idx) {
+  const PartChunk& C = P.chunks[(size_t)list[idx]];
+  for (size_t k = idx + 1; k < list.size(); ++k) {
+    const PartChunk& D = P.chunks[(size_t)list[k]];
+    if (D.bi != C.bi) return -1;
+    if (D.bj >= 0 && D.bj != C.bj) return D.bj;
+  }
+  return -1;
+}
 
 }  // namespace
 
@@ -346,28 +445,32 @@ void select_chunks(const PartPlan& P, const uint8_t* role, std::vector<int32_t>&
   const size_t nc = P.chunks.size();
   std::vector<uint8_t> need_m(nc, 0), need_a(nc, 0);
   const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  // blocks holding a core: a chunk whose two blocks hold none has nothing to do
+  // units and blocks holding a core: a chunk whose block and unit hold none
+  // has nothing to do
+  const int32_t U = (int32_t)P.unit_lo.size() - 1;
   const int32_t K = (int32_t)P.block_lo.size() - 1;
-  std::vector<uint8_t> block_core((size_t)(K > 0 ? K : 1), 0);
+  std::vector<uint8_t> unit_core((size_t)(U > 0 ? U : 1), 0), block_core((size_t)(K > 0 ? K : 1), 0);
   {
     std::vector<std::thread> th;
     for (unsigned t = 0; t < nth; ++t)
       th.emplace_back([&, t]() {
-        for (int32_t b = (int32_t)t; b < K; b += (int32_t)nth)
-          for (int32_t v = P.block_lo[(size_t)b]; v < P.block_lo[(size_t)b + 1]; ++v)
+        for (int32_t b = (int32_t)t; b < U; b += (int32_t)nth)
+          for (int32_t v = P.unit_lo[(size_t)b]; v < P.unit_lo[(size_t)b + 1]; ++v)
             if (role[v] == ROLE_CORE) {
-              block_core[(size_t)b] = 1;
+              unit_core[(size_t)b] = 1;
               break;
             }
       });
     for (auto& x : th) x.join();
+    for (int32_t b = 0; b < U; ++b)
+      if (unit_core[(size_t)b]) block_core[(size_t)(b / P.upb)] = 1;
   }
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nth; ++t)
     th.emplace_back([&, t]() {
       for (size_t c = t; c < nc; c += nth) {
         const PartChunk& C = P.chunks[c];
-        if (!block_core[(size_t)C.bi] && !block_core[(size_t)C.bj]) continue;
+        if (!block_core[(size_t)C.bi] && !(C.bj >= 0 && unit_core[(size_t)C.bj])) continue;
         bool m = false, a = false;
         for (int64_t e = C.begin; e < C.end && !(m && a); ++e) {
           const int2 uv = P.h_edges[e];
@@ -453,6 +556,9 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
     int idx = 0;
     for (const int32_t ci : list) {
       const PartChunk& C = P.chunks[(size_t)ci];
+      if (idx == 0 || C.bi != P.chunks[(size_t)list[(size_t)idx - 1]].bi ||
+          C.bj != P.chunks[(size_t)list[(size_t)idx - 1]].bj)
+        HIP_TRY(st.enter(C.bi, C.bj, next_unit(P, list, (size_t)idx), A), "rows H2D");
       const int64_t ne = C.end - C.begin;
       const int b = idx & 1;
       int2* de = b ? P.d_edges2 : P.d_edges;
@@ -467,8 +573,6 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
       HIP_TRY(hipEventRecord(P.up[b], P.copy), "hipEventRecord");
       P.h2d_bytes += (mode != MODE_CORES ? 9ull : 8ull) * (uint64_t)ne;
       ++P.chunks_streamed;
-      // block rows go on the compute stream: the previous chunk's kernels read the old ones
-      HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
       HIP_TRY(hipStreamWaitEvent(s, P.up[b], 0), "hipStreamWaitEvent");
       A.edges = de;
       A.state = ds;
@@ -480,6 +584,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
       HIP_TRY(hipEventRecord(P.done[b], s), "hipEventRecord");
       ++idx;
     }
+    HIP_TRY(st.finish(), "hipEventRecord");
     // the states copied back are read by the next pass's uploads and chunk selection
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(P.copy), "hipStreamSynchronize");
@@ -544,15 +649,20 @@ int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
   A.mu = 2;
   A.pruning = 0;
   Streamer st{g, s};
-  for (const PartChunk& C : P.chunks) {
+  std::vector<int32_t> all(P.chunks.size());
+  for (size_t c = 0; c < all.size(); ++c) all[c] = (int32_t)c;
+  for (size_t idx = 0; idx < all.size(); ++idx) {
+    const PartChunk& C = P.chunks[idx];
     const int64_t ne = C.end - C.begin;
-    HIP_TRY(st.rows(C.bi, C.bj, A), "rows H2D");
+    if (idx == 0 || C.bi != P.chunks[idx - 1].bi || C.bj != P.chunks[idx - 1].bj)
+      HIP_TRY(st.enter(C.bi, C.bj, next_unit(P, all, idx), A), "rows H2D");
     HIP_TRY(hipMemcpyAsync(P.d_edges, P.h_edges + C.begin, sizeof(int2) * (size_t)ne, hipMemcpyHostToDevice, s),
             "edges H2D");
     launch_chunk(s, MODE_COUNTS, C, A, P);
     HIP_TRY(hipMemcpyAsync(P.h_ecount + C.begin, P.d_ecount, sizeof(int32_t) * (size_t)ne, hipMemcpyDeviceToHost, s),
             "counts D2H");
   }
+  HIP_TRY(st.finish(), "hipEventRecord");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   // per-edge counts to both arcs (CSR order)
   const int64_t m = g->m;
