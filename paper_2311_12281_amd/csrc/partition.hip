@@ -3,11 +3,15 @@
 // Lemma 5.1; the three streamed passes of Alg. 5).
 //
 // Redesign for one MI355X: instead of packing edges greedily into subgraphs
-// (Alg. 5, host loop), vertices are cut into contiguous ranges ("blocks") whose
-// rows fit half of the device row buffer.  The edges between blocks i <= j are
-// processed with the complete rows of both blocks on the device, so every
-// intersection sees both full neighbourhoods - the edge-extended subgraph of
-// those edges - and sigma is exact (Lemma 5.1).  Per-vertex state (bounds,
+// (Alg. 5, host loop), vertices are cut into contiguous ranges ("units") whose
+// rows fit a quarter of the device row buffer, and consecutive pairs of units
+// form "blocks".  The edges between a block and a unit of a later block (or
+// inside a block) are processed with the complete rows of both on the device,
+// so every intersection sees both full neighbourhoods - the edge-extended
+// subgraph of those edges - and sigma is exact (Lemma 5.1).  The block sits
+// in the first half of the row buffer, units in two slots of the second half:
+// the next unit's rows are uploaded on a stream of their own while the current
+// one is read.  Per-vertex state (bounds,
 // roles, parents, labels) and row_ptr stay resident for the whole run; edge
 // states travel with their edges (uploaded before, read back after each chunk,
 // like the store step of Alg. 5).  One run streams the pairs three times: the
