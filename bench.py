@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--serve-upload-every", type=float, default=1.0, help="serving: seconds between uploads")
     ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-waiters", type=int, default=4, help="serving: client threads collecting results")
     ap.add_argument("--serve-plain-seconds", type=float, default=10.0,
                     help="serving: arrivals of the plain comparison (bounded run)")
     ap.add_argument("--batch-count", type=int, default=10000)
@@ -636,16 +637,30 @@ def bench_serving(args):
     def query(k, ngraphs):
         return int(picks[k] * ngraphs), int(eps_k[k]), 10, int(mus[k])
 
+    # results are collected by --serve-waiters client threads, each copying into buffers of its own
+    # (allocated once: a fresh array per result would be page-faulted in on every copy)
+    nwait = max(1, args.serve_waiters)
+    nmax = max(g.n for g in graphs + uploads)
+    bufs = [(np.empty(nmax, np.int32), np.empty(nmax, np.uint8)) for _ in range(nwait)]
+
     # saturation: the whole query list on the resident graphs, submitted at once
     t0 = time.perf_counter()
     reqs = [(srv.submit(gids[gi], p, q, mu), gi) for gi, p, q, mu in (query(k, len(gids)) for k in range(nq))]
-    sat_edges = 0.0
-    for r, gi in reqs:
-        srv.wait(r, gids[gi])
-        sat_edges += graphs[gi].m
+
+    def sat_waiter(t):
+        lb, rb = bufs[t]
+        for r, gi in reqs[t::nwait]:
+            srv.wait(r, gids[gi], lb, rb)
+
+    ths = [threading.Thread(target=sat_waiter, args=(t,)) for t in range(nwait)]
+    for x in ths:
+        x.start()
+    for x in ths:
+        x.join()
+    sat_edges = float(sum(graphs[gi].m for _, gi in reqs))
     sat_s = time.perf_counter() - t0
     sat = nq / sat_s
-    log(f"served saturation: {sat:.0f} queries/s, {sat_edges / sat_s / 1e9:.2f} G edges/s")
+    log(f"served saturation ({nwait} client threads): {sat:.0f} queries/s, {sat_edges / sat_s / 1e9:.2f} G edges/s")
 
     res_gids = list(gids)       # graphs queries may target (resident ones and uploads that became resident)
     upload_gids = []
@@ -656,13 +671,21 @@ def bench_serving(args):
         dig = [None] * nq
         keys = [None] * nq
         ready = threading.Semaphore(0)
+        take = threading.Lock()
+        nxt = [0]
         start = time.perf_counter()
 
-        def waiter():
-            for k in range(nq):
+        def waiter(t):
+            lb, rb = bufs[t]
+            while True:
                 ready.acquire()
+                with take:
+                    k = nxt[0]
+                    nxt[0] += 1
+                if k >= nq:
+                    return
                 r, gid = keys[k][0], keys[k][1]
-                lab, rol, ms = srv.wait(r, gid)
+                lab, rol, ms = srv.wait(r, gid, lb, rb)
                 lat[k] = ms
                 dig[k] = fast_digest(lab, rol)
 
@@ -682,8 +705,9 @@ def bench_serving(args):
                 if srv.info()["resident_graphs"] == len(res_gids) + 1:
                     res_gids.append(gid)
 
-        th = threading.Thread(target=waiter)
-        th.start()
+        ths = [threading.Thread(target=waiter, args=(t,)) for t in range(nwait)]
+        for x in ths:
+            x.start()
         up = threading.Thread(target=uploader) if with_uploads else None
         if up:
             up.start()
@@ -696,7 +720,10 @@ def bench_serving(args):
             gid = pool[gi]
             keys[k] = (srv.submit(gid, p, q, mu), gid, p, q, mu)
             ready.release()
-        th.join()
+        for _ in range(nwait):  # one stop token per waiter
+            ready.release()
+        for x in ths:
+            x.join()
         if up:
             up.join()
         wall = time.perf_counter() - start
@@ -739,6 +766,7 @@ def bench_serving(args):
         arr = np.cumsum(np.random.default_rng(int(qps)).exponential(1.0 / qps, size=cnt)) if qps else np.zeros(cnt)
         lat = []
         edges = 0.0
+        lb, rb = bufs[0]
         start = time.perf_counter()
         for k in range(cnt):
             if time.perf_counter() - start > args.serve_plain_seconds:
@@ -748,7 +776,7 @@ def bench_serving(args):
                 time.sleep(d)
             gi, p, q, mu = query(k, len(res_gids))
             gid = res_gids[gi]
-            plain_graphs[gid].run(p, q, mu)
+            plain_graphs[gid].run(p, q, mu, lb, rb)
             lat.append((time.perf_counter() - start - arr[k]) * 1e3)
             edges += all_graphs[g_index[gid]].m
         wall = time.perf_counter() - start
@@ -759,6 +787,32 @@ def bench_serving(args):
     plain_sat = len(lat) / wall
     plain = {"saturation_qps": plain_sat, "saturation_edges_per_s": edges / wall, "saturation_queries": len(lat)}
     log(f"plain saturation: {plain_sat:.0f} queries/s, {edges / wall / 1e9:.2f} G edges/s")
+
+    # plain with as many client threads as the served path's waiters (scan_run on different graphs
+    # runs concurrently; calls on one graph take turns)
+    done_q = [0] * nwait
+    done_e = [0.0] * nwait
+    t0 = time.perf_counter()
+
+    def plain_client(t):
+        lb, rb = bufs[t]
+        for k in range(t, nq, nwait):
+            if time.perf_counter() - t0 > args.serve_plain_seconds:
+                return
+            gi, p, q, mu = query(k, len(res_gids))
+            gid = res_gids[gi]
+            plain_graphs[gid].run(p, q, mu, lb, rb)
+            done_q[t] += 1
+            done_e[t] += all_graphs[g_index[gid]].m
+
+    ths = [threading.Thread(target=plain_client, args=(t,)) for t in range(nwait)]
+    for x in ths:
+        x.start()
+    for x in ths:
+        x.join()
+    wall = time.perf_counter() - t0
+    plain["saturation_threads"] = {"threads": nwait, "qps": sum(done_q) / wall, "edges_per_s": sum(done_e) / wall}
+    log(f"plain saturation, {nwait} client threads: {plain['saturation_threads']}")
     for frac in (0.5, 0.9):
         for label, qps in ((f"own_{frac}x", frac * plain_sat), (f"served_rate_{frac}x", frac * sat)):
             lat, edges, wall, backlog = run_plain(qps, nq)
@@ -798,7 +852,8 @@ def bench_serving(args):
     srv.close()
     _line("queries/s at saturation, served (cached counts, continuous batching)", sat, "queries/s",
           {"workload": f"serving_rmat{len(graphs)}+{len(uploads)}_s16-23_ef8-32", "resident_graphs": len(graphs),
-           "uploads": len(uploads), "queries": nq, "slots": nslots, "budget_bytes": budget},
+           "uploads": len(uploads), "queries": nq, "slots": nslots, "client_threads": nwait,
+           "budget_bytes": budget},
           saturation_edges_per_s=sat_edges / sat_s, add_graphs_s=add_s, oracle_digests_exact=oracle_ok,
           alone_run_exact=alone_ok, fallback=fallback, poisson=out, plain=plain)
 

@@ -340,8 +340,8 @@ class Graph:
     def info(self):
         return scan_graph_info(self.handle)
 
-    def run(self, p, q, mu):
-        return scan_run(self.handle, p, q, mu)
+    def run(self, p, q, mu, labels=None, roles=None):
+        return scan_run(self.handle, p, q, mu, labels, roles)
 
     def run_device(self, p, q, mu, d_labels, d_roles, stream=None):
         scan_run_device(self.handle, p, q, mu, d_labels, d_roles, stream)
@@ -402,9 +402,18 @@ def scan_server_submit(s, gid: int, eps_num: int, eps_den: int, mu: int) -> int:
     return req.value
 
 
-def scan_server_wait(s, req: int, n: int):
-    labels = np.empty(max(n, 1), dtype=np.int32)
-    roles = np.empty(max(n, 1), dtype=np.uint8)
+def scan_server_wait(s, req: int, n: int, labels=None, roles=None):
+    """Waits for request req of a graph of n vertices; its labels and roles go
+    to the given arrays (contiguous int32 / uint8 of at least n entries, reused
+    across calls by a caller that wants to avoid fresh allocations) or to new
+    ones.  Returns (labels[:n], roles[:n], latency in ms)."""
+    if labels is None:
+        labels = np.empty(max(n, 1), dtype=np.int32)
+    if roles is None:
+        roles = np.empty(max(n, 1), dtype=np.uint8)
+    if (labels.dtype != np.int32 or roles.dtype != np.uint8 or labels.size < max(n, 1) or roles.size < max(n, 1)
+            or not labels.flags.c_contiguous or not roles.flags.c_contiguous):
+        raise ValueError("labels / roles must be contiguous int32 / uint8 arrays of at least n entries")
     lat = ctypes.c_double()
     _check(lib().scan_server_wait(s, int(req), _vp(labels), _vp(roles), ctypes.byref(lat)))
     return labels[:n], roles[:n], lat.value
@@ -443,8 +452,8 @@ class Server:
     def submit(self, gid: int, p: int, q: int, mu: int) -> int:
         return scan_server_submit(self.handle, gid, p, q, mu)
 
-    def wait(self, req: int, gid: int):
-        return scan_server_wait(self.handle, req, self.sizes[gid])
+    def wait(self, req: int, gid: int, labels=None, roles=None):
+        return scan_server_wait(self.handle, req, self.sizes[gid], labels, roles)
 
     def info(self) -> dict:
         return scan_server_info(self.handle)
