@@ -551,15 +551,20 @@ __device__ __forceinline__ void group_edges(const EdgeArgs& A, int64_t begin, in
             __builtin_amdgcn_wave_barrier();
             for (int i = lane; i < kWaveBuckets; i += 64)
               reinterpret_cast<int4*>(T)[i] = make_int4(-1, -1, -1, -1);
-            int32_t y[kHubMinDegree / 64];
-#pragma unroll
-            for (int k = 0; k < kHubMinDegree / 64; ++k)
-              y[k] = (k * 64 + lane < w.dv) ? A.ci[w.bv + k * 64 + lane] : -1;
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            // two loads in flight per lane, then their inserts: holding all
+            // eight of a 512-element list spilled registers in the fused
+            // batch kernel
+            for (int k0 = 0; k0 < kHubMinDegree / 64 && k0 * 64 < w.dv; k0 += 2) {
+              int32_t y[2];
 #pragma unroll
-            for (int k = 0; k < kHubMinDegree / 64; ++k)
-              if (y[k] >= 0) wave_insert(T, y[k]);
+              for (int k = 0; k < 2; ++k)
+                y[k] = ((k0 + k) * 64 + lane < w.dv) ? A.ci[w.bv + (k0 + k) * 64 + lane] : -1;
+#pragma unroll
+              for (int k = 0; k < 2; ++k)
+                if (y[k] >= 0) wave_insert(T, y[k]);
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             staged_v = w.v;

@@ -73,7 +73,7 @@ constexpr int kHubGroup = 8;      // lanes streaming one survivor
 constexpr int kHubUnroll = 8;      // elements per lane per step
 constexpr int kHubChunk = 1024;    // elements of one survivor handed to a group at a time
 // col_idx is allocated with this many spare elements after its end, so that the
-// LDS-hash kernel's step loads (up to two steps past a chunk's end, values
+// LDS-hash kernel's step loads (up to one step past a chunk's end, values
 // beyond the end ignored) need no clamping
 constexpr int64_t kColPad = 2 * kHubGroup * kHubUnroll;
 constexpr int kHubLog2Slots = 14;  // LDS table per block: 16384 int32 slots = 64 KiB
