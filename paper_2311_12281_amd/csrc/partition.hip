@@ -22,6 +22,7 @@
 #include "graph.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -469,24 +470,49 @@ void select_chunks(const PartPlan& P, const uint8_t* role, std::vector<int32_t>&
     for (int32_t b = 0; b < U; ++b)
       if (unit_core[(size_t)b]) block_core[(size_t)(b / P.upb)] = 1;
   }
+  // slices of kSlice edges, taken by the threads from a shared counter, so
+  // that a chunk needing a full scan (no qualifying edge early on) is spread
+  // over all of them; a slice stops once both of its chunk's flags are set
+  constexpr int64_t kSlice = 1 << 20;
+  std::vector<int64_t> first_slice(nc + 1, 0);
+  for (size_t c = 0; c < nc; ++c) {
+    const PartChunk& C = P.chunks[c];
+    const bool live = block_core[(size_t)C.bi] || (C.bj >= 0 && unit_core[(size_t)C.bj]);
+    first_slice[c + 1] = first_slice[c] + (live ? (C.end - C.begin + kSlice - 1) / kSlice : 0);
+  }
+  std::vector<std::atomic<uint8_t>> fm(nc), fa(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    fm[c].store(0, std::memory_order_relaxed);
+    fa[c].store(0, std::memory_order_relaxed);
+  }
+  std::atomic<int64_t> next{0};
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nth; ++t)
-    th.emplace_back([&, t]() {
-      for (size_t c = t; c < nc; c += nth) {
+    th.emplace_back([&]() {
+      for (int64_t k = next.fetch_add(1); k < first_slice[nc]; k = next.fetch_add(1)) {
+        const size_t c = (size_t)(std::upper_bound(first_slice.begin(), first_slice.end(), k) - first_slice.begin()) - 1;
         const PartChunk& C = P.chunks[c];
-        if (!block_core[(size_t)C.bi] && !(C.bj >= 0 && unit_core[(size_t)C.bj])) continue;
-        bool m = false, a = false;
-        for (int64_t e = C.begin; e < C.end && !(m && a); ++e) {
+        const int64_t b = C.begin + (k - first_slice[c]) * kSlice, e_end = std::min(C.end, b + kSlice);
+        bool m = fm[c].load(std::memory_order_relaxed) != 0, a = fa[c].load(std::memory_order_relaxed) != 0;
+        for (int64_t e = b; e < e_end && !(m && a); ++e) {
           const int2 uv = P.h_edges[e];
           const bool cu = role[uv.x] == ROLE_CORE, cv = role[uv.y] == ROLE_CORE;
           m = m || (cu && cv);
           a = a || (cu != cv && P.h_state[e] != SIM_NO);
+          if ((e & 4095) == 4095) {  // another slice of the chunk may have found what is missing
+            m = m || fm[c].load(std::memory_order_relaxed) != 0;
+            a = a || fa[c].load(std::memory_order_relaxed) != 0;
+          }
         }
-        need_m[c] = m;
-        need_a[c] = a;
+        if (m) fm[c].store(1, std::memory_order_relaxed);
+        if (a) fa[c].store(1, std::memory_order_relaxed);
       }
     });
   for (auto& x : th) x.join();
+  for (size_t c = 0; c < nc; ++c) {
+    need_m[c] = fm[c].load();
+    need_a[c] = fa[c].load();
+  }
   merge_list.clear();
   attach_list.clear();
   for (size_t c = 0; c < nc; ++c) {
