@@ -191,6 +191,28 @@ def main():
     dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
     traffic = _traffic_from_profile(dom_kernel)
     # every bucket's kernel against the same roofline, and the whole cores pass
+    # byte models of a whole solve: the measured intersections (4 bytes per element consumed + 9 per
+    # intersected edge, every bucket) plus each row read once as the probe side (4 nnz), the offsets
+    # (8 (n + 1)) and the per-vertex state (17 n); beside them, for a solve that evaluates every edge
+    # without pruning, whole smaller lists (4 sum_e min(d_u, d_v) + 9 m) and both lists (the merge
+    # model, 4 sum_e (d_u + d_v) = 4 sum_v d_v^2)
+    deg = np.diff(np.asarray(g.row_ptr)).astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    dst = np.asarray(g.col_idx, dtype=np.int64)
+    own = src < dst
+    sum_min = int(np.minimum(deg[src[own]], deg[dst[own]]).sum())
+    sum_both = int((deg * deg).sum())
+    del src, dst, own
+    fixed = 4.0 * g.nnz + 8.0 * (n + 1) + 17.0 * n
+    byte_models = {
+        "per_eps_probe_model_bytes": [
+            float(4.0 * np.sum(s_["cores_bucket_probes"]) + 9.0 * np.sum(s_["cores_bucket_evaluated"]) + fixed)
+            for s_ in stats[-len(EPS_SET):]],
+        "full_evaluation_min_model_bytes": 4.0 * sum_min + 9.0 * m + fixed,
+        "full_evaluation_merge_model_bytes": 4.0 * sum_both,
+        "dominant_kernel_traffic_over_alg": (traffic / float(bytes_b[dom] / launches)) if traffic else None,
+    }
+    log(f"byte models: {byte_models}")
     # (the intersection bytes above, and beside them the same plus the classification stream:
     # 8 bytes of endpoints, 8 of degrees and 1 of edge state for every edge of the bucket)
     buckets = []
@@ -318,6 +340,7 @@ def main():
         "eps_1_10": eps10,
         "cores_pass": cores_pass,
         "buckets": buckets,
+        "byte_models": byte_models,
     }
     S.scan_device_free(dl10)
     S.scan_device_free(dr10)
@@ -340,6 +363,11 @@ def _cpu_model():
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_hub_cores_rmat22.md")
+# counter passes beside the traffic ones (each within one pass's per-block limits)
+LDS_COUNTERS = ["SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS", "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD",
+                "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY"]
+ATOMIC_COUNTERS = ["TCC_ATOMIC_sum", "TCC_EA0_ATOMIC_sum", "TCP_TCC_ATOMIC_WITH_RET_REQ_sum",
+                   "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"]
 KERNEL_SOURCES = ["kernels.hip", "layout.hip", "api.hip", "scan_internal.h"]
 
 
@@ -439,6 +467,8 @@ rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o bench 
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
 rocprofv3 --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_rdreq -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
 rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_RDREQ_sum --output-format csv -d gpurun_out/pmc_dram -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
+rocprofv3 --pmc {' '.join(LDS_COUNTERS)} --output-format csv -d gpurun_out/pmc_lds -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
+rocprofv3 --pmc {' '.join(ATOMIC_COUNTERS)} --output-format csv -d gpurun_out/pmc_atomic -o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-verify --no-eps10
 {cmd}
 ```
 
@@ -464,6 +494,26 @@ those that went to DRAM:
 - kernel_sources_sha256: `{_kernel_source_hash()}`
 - traffic_bytes_per_launch: {traffic:.0f}
 """)
+    # any further counters of the runs (LDS, atomics, instructions): per-dispatch means for the kernel
+    known = {"FETCH_SIZE", "WRITE_SIZE", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+             "TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_DRAM_sum"}
+    extra = sorted({c for _, nm, c, _ in rows if c not in known and is_k(nm)})
+    if extra:
+        print("Further counters of the kernel (per dispatch, mean over dispatches; SQ counters are sums over\n"
+              "the shader engines, LDS cycle counters in the units rocprofv3 reports):\n")
+        print("| counter | value |")
+        print("|---|---|")
+        vals = {}
+        for c in extra:
+            v, nd = _per_dispatch_mean(rows, c, is_k)
+            vals[c] = v
+            print(f"| {c} | {v:.4g} ({nd} dispatches) |")
+        if vals.get("SQ_LDS_IDX_ACTIVE") and "SQ_LDS_BANK_CONFLICT" in vals:
+            act, bc = vals["SQ_LDS_IDX_ACTIVE"], vals["SQ_LDS_BANK_CONFLICT"]
+            print(f"\n- LDS bank-conflict cycles per conflict-free LDS cycle: {bc / max(act - bc, 1.0):.3f}")
+        if vals.get("SQ_INSTS_LDS") and vals.get("SQ_INSTS_VALU"):
+            print(f"- VALU instructions per LDS instruction: {vals['SQ_INSTS_VALU'] / vals['SQ_INSTS_LDS']:.2f}")
+        print()
     bt = _bucket_traffic(rows, sf, sw)
     print("Every cores-pass kernel, by degree bucket (scaled FETCH_SIZE and WRITE_SIZE per dispatch, GB;")
     print("dispatches are those of the FETCH and WRITE runs together):\n")
