@@ -11,11 +11,12 @@
 using namespace scan;
 
 // Partitioned (out-of-core) layout: GPUSCAN++ Section 5 (Def. 5.1, Lemma 5.1,
-// Alg. 5).  The CSR stays in pinned host memory; vertex ranges ("blocks")
-// are sized so that two blocks' rows fit the device row buffer, and every
-// edge belongs to the pair of blocks of its endpoints.  A chunk is a run of
-// one pair's edges (grouped by degree bucket) small enough for the device
-// edge buffer.
+// Alg. 5).  The CSR stays in pinned host memory; vertex ranges ("units") are
+// sized so that a block (two consecutive units) fits half of the device row
+// buffer and a unit one of the two slots of its other half, and every edge
+// belongs to the pair of its lower endpoint's block with the other endpoint's
+// unit (or to the block's own pair).  A chunk is a run of one pair's edges
+// (grouped by degree bucket) small enough for the device edge buffer.
 struct PartChunk {
   int32_t bi, bj;                          // block bi with unit bj of a later block (-1: edges inside bi)
   int64_t begin, end;                      // range of the pinned edge array
@@ -35,7 +36,7 @@ struct PartPlan {
   int2* h_edges = nullptr;        // pinned: oriented edges ordered by (pair, bucket, arc)
   uint8_t* h_state = nullptr;     // pinned: edge states, streamed with the edges
   int32_t* h_ecount = nullptr;    // pinned: per-edge closed counts (scan_similarity)
-  int64_t row_cap = 0;            // ints of the device row buffer (two blocks)
+  int64_t row_cap = 0;            // ints of the device row buffer (a block, then the unit slots)
   int64_t chunk_cap = 0;          // edges per chunk
   int32_t* d_rows = nullptr;
   int2* d_edges = nullptr;        // two chunk buffers (edges, states): the next chunk is
