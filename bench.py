@@ -178,7 +178,7 @@ def main():
     csrc_ = S.scan_device_alloc(copy_bytes)
     cdst_ = S.scan_device_alloc(copy_bytes)
     copy_ms = S.scan_device_copy(cdst_, csrc_, copy_bytes, iters=5)
-    read_bytes = 2 * copy_bytes  # the read-only stream covers both buffers
+    read_bytes = 8 * copy_bytes  # long enough for a steady rate
     S.scan_device_free(cdst_)
     S.scan_device_free(csrc_)
     copy_gbps = 2.0 * copy_bytes / (copy_ms * 1e-3) / 1e9

@@ -1275,13 +1275,18 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
-// Plain streaming read, 16 bytes per lane per step, folded into one word per
-// thread (written so that the reads are not removed): the achievable rate of a
-// read-only stream, the ceiling for kernels that mostly read.
+// Plain streaming read, 16 bytes per lane per load and four independent loads
+// per lane in flight, folded into one word per thread (written so that the
+// reads are not removed): the achievable rate of a read-only stream, the
+// ceiling for kernels that mostly read.
 __global__ void k_read16(const uint4* __restrict__ src, int64_t n16, uint32_t* __restrict__ sink) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t acc = 0;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
   for (; i < n16; i += stride) {
     const uint4 v = src[i];
     acc ^= v.x ^ v.y ^ v.z ^ v.w;
