@@ -373,8 +373,14 @@ struct Streamer {
         for (int q = 0; q < P.nslots; ++q)
           if (slot_unit[q] == u) k = q;
         if (k >= 0) {
-          e = hipMemcpyAsync(P.d_rows + at, P.d_rows + slot_off(k), sizeof(int32_t) * (size_t)len,
-                             hipMemcpyDeviceToDevice, s);
+          // the slot's upload has been waited for already (every unit a slot
+          // receives is the unit of a later run of the same block, entered
+          // before this block comes up); the wait is repeated here so that the
+          // copy does not depend on that order
+          e = hipStreamWaitEvent(s, P.rready[k], 0);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(P.d_rows + at, P.d_rows + slot_off(k), sizeof(int32_t) * (size_t)len,
+                               hipMemcpyDeviceToDevice, s);
         } else {
           e = hipMemcpyAsync(P.d_rows + at, P.h_ci + b, sizeof(int32_t) * (size_t)len, hipMemcpyHostToDevice, s);
           P.h2d_bytes += 4ull * (uint64_t)len;
