@@ -26,9 +26,20 @@
  * code; on error the output buffers are left in an unspecified state and
  * scan_last_error() describes the failure.  No function throws.
  *
- * Threading: a scan_graph is immutable after creation.  Calls on one graph
- * are serialised internally (they share the graph's per-run device buffers);
- * calls on different graphs may run concurrently.
+ * Threading: a scan_graph is immutable after creation, and every function may
+ * be called from several threads at once.  scan_run and scan_run_device calls
+ * on one in-memory graph overlap: a call that finds the graph's per-run
+ * device buffers in use by another call runs beside it on a buffer set of its
+ * own (17 n + m + 4 b + 256 bytes, b the edges of the last degree bucket,
+ * plus 5 n of output staging for scan_run), on its own stream or the
+ * caller's.  The sets are
+ * allocated at the first overlap that needs them and kept for later calls
+ * until scan_graph_destroy (scan_graph_device_bytes counts them).  A call
+ * waits for the graph's own buffers instead when the graph was created with
+ * device_budget_bytes and another set would exceed it.  Calls on a
+ * partitioned graph and scan_similarity calls on one graph run one at a time.
+ * scan_last_stats reports the call that finished last.  Calls on different
+ * graphs are independent.
  */
 #ifndef SCAN_MI355X_SCAN_H
 #define SCAN_MI355X_SCAN_H
@@ -122,6 +133,12 @@ int scan_graph_footprint(int32_t n, int64_t nnz, const scan_opts* opts, uint64_t
 
 /* Sizes of a created graph: vertices, arcs, undirected edges, maximum degree. */
 int scan_graph_info(const scan_graph* g, int32_t* n, int64_t* nnz, int64_t* m, int32_t* max_degree);
+
+/* Device bytes an in-memory graph holds now: its layout, its per-run buffers
+ * and staging as allocated so far, and the buffer sets of overlapping calls
+ * (0 for a partitioned graph, whose device use is its budget).
+ * SCAN_E_INVAL if an argument is NULL. */
+int scan_graph_device_bytes(const scan_graph* g, uint64_t* bytes);
 
 /*
  * scan_run - structural clustering of g for eps = eps_num/eps_den and mu

@@ -33,7 +33,7 @@ EXPORTED = [
     "scan_server_wait", "scan_server_info", "scan_server_destroy",
     "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats", "scan_batch_destroy",
     "scan_run_batch", "scan_run_device_noalloc", "scan_graph_footprint", "scan_batch_set_params",
-    "scan_server_set_budget", "scan_device_read",
+    "scan_server_set_budget", "scan_device_read", "scan_graph_device_bytes",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
         L.scan_graph_destroy.argtypes = [vp]
         L.scan_graph_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
         L.scan_graph_footprint.argtypes = [i32, i64, P(scan_opts), P(u64)]
+        L.scan_graph_device_bytes.argtypes = [vp, P(u64)]
         L.scan_run.argtypes = [vp, i64, i64, i32, vp, vp]
         L.scan_run_device.argtypes = [vp, i64, i64, i32, vp, vp, vp]
         L.scan_run_device_noalloc.argtypes = [vp, i64, i64, i32, vp, vp, vp]
@@ -150,7 +151,7 @@ def lib():
                      "scan_batch_create", "scan_batch_run", "scan_batch_config", "scan_batch_stats",
                      "scan_batch_destroy", "scan_run_batch", "scan_run_device_noalloc",
                      "scan_graph_footprint", "scan_batch_set_params", "scan_server_set_budget",
-                     "scan_device_read"):
+                     "scan_device_read", "scan_graph_device_bytes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,6 +217,12 @@ def scan_graph_footprint(n: int, nnz: int, opts: scan_opts | None = None) -> int
     b = ctypes.c_uint64()
     _check(lib().scan_graph_footprint(int(n), int(nnz), ctypes.byref(opts) if opts is not None else None,
                                       ctypes.byref(b)))
+    return int(b.value)
+
+
+def scan_graph_device_bytes(g) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().scan_graph_device_bytes(g, ctypes.byref(b)))
     return int(b.value)
 
 
@@ -339,6 +346,9 @@ class Graph:
 
     def info(self):
         return scan_graph_info(self.handle)
+
+    def device_bytes(self):
+        return scan_graph_device_bytes(self.handle)
 
     def run(self, p, q, mu, labels=None, roles=None):
         return scan_run(self.handle, p, q, mu, labels, roles)

@@ -41,8 +41,25 @@ int fail_hip(hipError_t e, const char* what) {
 
 namespace {
 
+void release_extra(ExtraRun& x) {
+  void* ptrs[] = {x.R.lower, x.R.upper, x.R.role, x.R.parent, x.R.label, x.R.state, x.R.stats,
+                  x.R.counters, x.R.worklist, x.d_out_labels, x.d_out_roles};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  for (auto& e : x.ev)
+    if (e) hipEventDestroy(e);
+  if (x.stream) hipStreamDestroy(x.stream);
+  x = ExtraRun();
+}
+
 void release(scan_graph* g) {
   part_release(g);
+  for (auto& x : g->extra) {
+    if (x->stream) hipStreamSynchronize(x->stream);
+    release_extra(*x);
+  }
+  g->extra.clear();
+  g->extra_bytes = 0;
   void* ptrs[] = {g->d_rp, g->d_ci, g->d_hci, g->d_hsamp, g->d_edges, g->d_edeg, g->d_jobs, g->d_wtab, g->d_worklist, g->d_counters, g->d_lower, g->d_upper, g->d_role, g->d_parent,
                   g->d_label, g->d_state, g->d_stats, g->d_out_labels, g->d_out_roles, g->d_counts};
   for (void* p : ptrs)
@@ -84,12 +101,13 @@ void scan::launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs
 // graph.  Per-graph parameters come from A.gid/gp/gq/gmu when set.
 void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
                               const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg,
-                              const RunState* state) {
+                              const RunState* state, hipEvent_t* events) {
   const int n = g->n;
   const int64_t m = g->m;
   const RunState R = state ? *state : graph_state(g);
+  hipEvent_t* ev = events ? events : g->ev;
   auto mark = [&](int k) {
-    if (timing) (void)hipEventRecord(g->ev[k], s);
+    if (timing) (void)hipEventRecord(ev[k], s);
   };
   A.rp = g->d_rp;
   A.ci = g->d_ci;
@@ -141,13 +159,22 @@ void scan::enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uin
 }
 
 // Reads the statistics counters and event times of the last enqueued run.
+void scan::set_last(scan_graph* g, const scan_stats& L) {
+  std::lock_guard<std::mutex> lk(g->stats_lock);
+  g->last = L;
+}
+
 int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
+  return collect_stats(g, s, timing, graph_state(g), g->ev);
+}
+
+int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing, const RunState& R, hipEvent_t* ev) {
   const int64_t m = g->m;
   HIP_TRY(hipGetLastError(), "kernel launch");
   unsigned long long st[ST_COUNT];
-  HIP_TRY(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
+  HIP_TRY(hipMemcpyAsync(st, R.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  scan_stats& L = g->last;
+  scan_stats L;
   memset(&L, 0, sizeof(L));
   L.edges = m;
   for (int k = 0; k < kNumBuckets; ++k) {
@@ -165,16 +192,17 @@ int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing) {
   if (timing) {
     float ms = 0;
     for (int ph = 0; ph < SCAN_NUM_PHASES; ++ph) {
-      hipEventElapsedTime(&ms, g->ev[ph], g->ev[ph + 1]);
+      hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
       L.ms_phase[ph] = ms;
     }
-    hipEventElapsedTime(&ms, g->ev[0], g->ev[SCAN_NUM_PHASES]);
+    hipEventElapsedTime(&ms, ev[0], ev[SCAN_NUM_PHASES]);
     L.ms_total = ms;
     for (int k = 0; k < kNumBuckets; ++k) {
-      hipEventElapsedTime(&ms, g->ev[k == 0 ? 1 : SCAN_NUM_PHASES + k], g->ev[SCAN_NUM_PHASES + 1 + k]);
+      hipEventElapsedTime(&ms, ev[k == 0 ? 1 : SCAN_NUM_PHASES + k], ev[SCAN_NUM_PHASES + 1 + k]);
       L.ms_cores_bucket[k] = ms;
     }
   }
+  set_last(g, L);
   return SCAN_OK;
 }
 
@@ -189,7 +217,7 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
   if (g->d_out_labels) b += 5 * n;
   if (g->d_counts) b += 4 * nnz;
-  return b;
+  return b + g->extra_bytes.load();
 }
 
 int scan::check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu) {
@@ -224,6 +252,109 @@ int run_clustering(scan_graph* g, int64_t p, int64_t q, int32_t mu, int32_t* d_l
   return collect_stats(g, s, timing);
 }
 
+// Device bytes of one extra buffer set (per-run state, and staging for host
+// outputs).
+uint64_t extra_run_bytes(const scan_graph* g, bool host) {
+  const uint64_t n = (uint64_t)g->n, m = (uint64_t)g->m;
+  const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
+  return 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters + 4 * b6 + (host ? 5 * n : 0);
+}
+
+// Allocates what x lacks; the bytes were reserved when x was taken.
+hipError_t alloc_extra(scan_graph* g, ExtraRun& x, bool host) {
+  hipError_t e = hipSuccess;
+  auto get = [&](auto** p, int64_t count) {
+    if (e == hipSuccess && !*p) e = hipMalloc((void**)p, sizeof(**p) * (size_t)(count > 0 ? count : 1));
+  };
+  const int64_t n = g->n, m = g->m;
+  get(&x.R.lower, n);
+  get(&x.R.upper, n);
+  get(&x.R.role, n);
+  get(&x.R.parent, n);
+  get(&x.R.label, n);
+  get(&x.R.state, m);
+  get(&x.R.stats, ST_COUNT);
+  get(&x.R.counters, kCounters);
+  get(&x.R.worklist, g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
+  if (host) {
+    get(&x.d_out_labels, n);
+    get(&x.d_out_roles, n);
+  }
+  if (e == hipSuccess && !x.stream) e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+  for (auto& ev : x.ev)
+    if (e == hipSuccess && !ev) e = hipEventCreate(&ev);
+  return e;
+}
+
+// For a call that found the graph's own per-run buffers in use: a free buffer
+// set of the graph's pool (one with staging when the outputs go to host
+// memory), or a new one, its device bytes reserved at once.  Null when the
+// call should wait for the graph's own buffers instead: on a partitioned
+// graph (its streaming buffers are single), or when a graph created under a
+// device budget has no room for another set, or when the calling thread's
+// current device is not the graph's (the set would be allocated there).
+ExtraRun* take_extra(scan_graph* g, bool host) {
+  if (g->partitioned) return nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g->device) return nullptr;
+  std::lock_guard<std::mutex> lk(g->pool_lock);
+  ExtraRun* x = nullptr;
+  for (auto& c : g->extra)
+    if (!c->busy && (!x || (host && c->d_out_labels && !x->d_out_labels))) x = c.get();
+  const uint64_t want = extra_run_bytes(g, host || (x && x->d_out_labels));
+  const uint64_t more = x ? want - std::min(want, x->bytes) : want;
+  const uint64_t budget = g->opts.device_budget_bytes;
+  if (budget && more && graph_device_bytes(g) + more > budget) return nullptr;
+  if (!x) {
+    g->extra.push_back(std::make_unique<ExtraRun>());
+    x = g->extra.back().get();
+  }
+  g->extra_bytes += more;
+  x->bytes += more;
+  x->busy = true;
+  return x;
+}
+
+// A clustering call on buffer set x of the graph's pool, on x's own stream
+// (or the caller's), beside the call that holds the graph's own buffers.
+// Host outputs go through x's staging.
+int run_extra(scan_graph* g, ExtraRun* x, int64_t p, int64_t q, int32_t mu, int32_t* d_labels,
+              uint8_t* d_roles, int32_t* h_labels, uint8_t* h_roles, hipStream_t caller) {
+  auto give_back = [&]() {
+    std::lock_guard<std::mutex> lk(g->pool_lock);
+    x->busy = false;
+  };
+  int rc = check_params(g, p, q, mu);
+  if (rc != SCAN_OK) {
+    give_back();
+    return rc;
+  }
+  const bool host = h_labels != nullptr;
+  const hipError_t e = alloc_extra(g, *x, host);
+  if (e != hipSuccess) {
+    give_back();
+    return fail_hip(e, "buffers for an overlapping call");
+  }
+  hipStream_t s = caller ? caller : x->stream;
+  EdgeArgs A{};
+  A.p = (uint64_t)p;
+  A.q = (uint64_t)q;
+  A.mu = mu;
+  A.pruning = g->opts.pruning;
+  const bool timing = g->opts.timing != 0;
+  enqueue_clustering(g, A, host ? x->d_out_labels : d_labels, host ? x->d_out_roles : d_roles, nullptr, s, timing,
+                     nullptr, &x->R, x->ev);
+  rc = collect_stats(g, s, timing, x->R, x->ev);
+  if (rc == SCAN_OK && host && g->n > 0) {
+    hipError_t c = hipMemcpyAsync(h_labels, x->d_out_labels, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, s);
+    if (c == hipSuccess) c = hipMemcpyAsync(h_roles, x->d_out_roles, (size_t)g->n, hipMemcpyDeviceToHost, s);
+    if (c == hipSuccess) c = hipStreamSynchronize(s);
+    if (c != hipSuccess) rc = fail_hip(c, "copy outputs");
+  }
+  give_back();
+  return rc;
+}
+
 }  // namespace
 
 int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hipStream_t s) {
@@ -252,7 +383,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
   unsigned long long st[ST_COUNT];
   HIP_TRY(hipMemcpyAsync(st, g->d_stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats copy");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  scan_stats& L = g->last;
+  scan_stats L;
   memset(&L, 0, sizeof(L));
   L.edges = g->m;
   L.evaluated[SCAN_PHASE_CORES] = (int64_t)st[ST_EVAL + MODE_COUNTS];
@@ -265,6 +396,7 @@ int scan::run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edg
     L.ms_total = ms;
     L.ms_phase[SCAN_PHASE_CORES] = ms;
   }
+  set_last(g, L);
   return SCAN_OK;
 }
 
@@ -447,7 +579,12 @@ int scan_run_device(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu,
   g_error.clear();
   if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
   if (g->n > 0 && (!d_labels || !d_roles)) return fail(SCAN_E_INVAL, "output pointer is NULL");
-  std::lock_guard<std::mutex> lk(g->lock);
+  std::unique_lock<std::mutex> lk(g->lock, std::try_to_lock);
+  if (!lk.owns_lock()) {
+    if (ExtraRun* x = take_extra(g, false))
+      return run_extra(g, x, eps_num, eps_den, mu, d_labels, d_roles, nullptr, nullptr, (hipStream_t)stream);
+    lk.lock();
+  }
   hipStream_t s = stream ? (hipStream_t)stream : g->stream;
   return run_clustering(g, eps_num, eps_den, mu, d_labels, d_roles, s);
 }
@@ -457,7 +594,12 @@ int scan_run(scan_graph* g, int64_t eps_num, int64_t eps_den, int32_t mu, int32_
   g_error.clear();
   if (!g) return fail(SCAN_E_INVAL, "graph is NULL");
   if (g->n > 0 && (!labels || !roles)) return fail(SCAN_E_INVAL, "output pointer is NULL");
-  std::lock_guard<std::mutex> lk(g->lock);
+  std::unique_lock<std::mutex> lk(g->lock, std::try_to_lock);
+  if (!lk.owns_lock()) {
+    if (ExtraRun* x = take_extra(g, true))
+      return run_extra(g, x, eps_num, eps_den, mu, nullptr, nullptr, labels, roles, nullptr);
+    lk.lock();
+  }
   if (!g->d_out_labels) {
     HIP_TRY(dalloc(&g->d_out_labels, g->n), "hipMalloc");
     HIP_TRY(dalloc(&g->d_out_roles, g->n), "hipMalloc");
@@ -502,7 +644,14 @@ int scan_similarity(scan_graph* g, int32_t* counts) {
 
 int scan_last_stats(const scan_graph* g, scan_stats* out) {
   if (!g || !out) return fail(SCAN_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(const_cast<scan_graph*>(g)->stats_lock);
   *out = g->last;
+  return SCAN_OK;
+}
+
+int scan_graph_device_bytes(const scan_graph* g, uint64_t* bytes) {
+  if (!g || !bytes) return fail(SCAN_E_INVAL, "NULL argument");
+  *bytes = graph_device_bytes(g);
   return SCAN_OK;
 }
 

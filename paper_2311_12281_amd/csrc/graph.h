@@ -5,10 +5,45 @@
 #include "scan_internal.h"
 #include "../../include/scan.h"
 
+#include <atomic>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <vector>
 
 using namespace scan;
+
+namespace scan {
+
+// Device buffers one clustering run works in: the graph's own (graph_state),
+// a set of the graph's pool for calls that overlap (ExtraRun), or a
+// caller-provided region of the same sizes.
+struct RunState {
+  int32_t* lower;
+  int32_t* upper;
+  uint8_t* role;
+  int32_t* parent;
+  int32_t* label;
+  uint8_t* state;                // one per oriented edge
+  unsigned long long* stats;     // ST_COUNT
+  unsigned long long* counters;  // kCounters
+  int32_t* worklist;             // one per edge of the last bucket
+};
+
+// Per-run buffers, stream and events of a call that overlaps another call on
+// the same in-memory graph; allocated at the first overlap and kept, for the
+// next one, until the graph is destroyed.
+struct ExtraRun {
+  RunState R{};
+  int32_t* d_out_labels = nullptr;  // staging for host outputs
+  uint8_t* d_out_roles = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[SCAN_NUM_PHASES + kNumBuckets + 2] = {};
+  uint64_t bytes = 0;  // device bytes it holds
+  bool busy = false;
+};
+
+}  // namespace scan
 
 // Partitioned (out-of-core) layout: GPUSCAN++ Section 5 (Def. 5.1, Lemma 5.1,
 // Alg. 5).  The CSR stays in pinned host memory; vertex ranges ("units") are
@@ -92,7 +127,12 @@ struct scan_graph {
   uint8_t* d_out_roles = nullptr;
   int32_t* d_counts = nullptr;      // staging for scan_similarity
   hipEvent_t ev[SCAN_NUM_PHASES + kNumBuckets + 2] = {};
-  std::mutex lock;
+  std::mutex lock;  // the graph's own per-run buffers, staging and events (one call at a time)
+  // buffer sets of calls that find the graph's own ones in use
+  std::mutex pool_lock;  // extra and the sets' busy flags
+  std::vector<std::unique_ptr<ExtraRun>> extra;
+  std::atomic<uint64_t> extra_bytes{0};
+  std::mutex stats_lock;  // last
   scan_stats last{};
 };
 
@@ -101,20 +141,9 @@ namespace scan {
 // Job counters of the LDS-hash kernel (one per pass), then the number of cores.
 constexpr int kCounters = 5;
 
-// Device buffers one clustering run works in: the graph's own (graph_state),
-// or a caller-provided region of the same sizes.
-struct RunState {
-  int32_t* lower;
-  int32_t* upper;
-  uint8_t* role;
-  int32_t* parent;
-  int32_t* label;
-  uint8_t* state;                // one per oriented edge
-  unsigned long long* stats;     // ST_COUNT
-  unsigned long long* counters;  // kCounters
-  int32_t* worklist;             // one per edge of the last bucket
-};
 RunState graph_state(scan_graph* g);
+// Publishes the statistics of a finished call (scan_last_stats reads them).
+void set_last(scan_graph* g, const scan_stats& L);
 
 // Per-bucket kernel choice for one run: lanes[k] = lane-group width of the
 // group kernel for bucket k (0 = the bucket's default), hub = LDS-hash kernel
@@ -128,14 +157,18 @@ void launch_bucket(scan_graph* g, hipStream_t s, int mode, int k, EdgeArgs& A, c
                    const RunConfig* cfg = nullptr);
 // Kernel launches of one clustering run (capturable); A carries eps/mu (or
 // per-graph arrays); gbase (batch) turns labels into graph-local ids.  The run
-// works in R, or in the graph's own buffers when R is null.
+// works in R, or in the graph's own buffers when R is null, and marks its
+// phases (timing) with the events ev, or the graph's own when ev is null.
 void enqueue_clustering(scan_graph* g, EdgeArgs& A, int32_t* d_labels, uint8_t* d_roles,
                         const int32_t* gbase, hipStream_t s, bool timing, const RunConfig* cfg,
-                        const RunState* R = nullptr);
+                        const RunState* R = nullptr, hipEvent_t* ev = nullptr);
 // Checks eps = p/q and mu against the graph (Def 2.3, Def 2.4, the 64-bit
 // range of the test) and reduces p/q; SCAN_OK or the error code.
 int check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu);
+// Waits for the run enqueued on s and publishes its statistics, read from R's
+// counters and the events ev (the graph's own buffers and events by default).
 int collect_stats(scan_graph* g, hipStream_t s, bool timing);
+int collect_stats(scan_graph* g, hipStream_t s, bool timing, const RunState& R, hipEvent_t* ev);
 
 // Sets the thread-local message returned by scan_last_error; returns code.
 int fail(int code, const char* fmt, ...);

@@ -643,7 +643,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
   unsigned long long stv[ST_COUNT];
   HIP_TRY(hipMemcpyAsync(stv, g->d_stats, sizeof(stv), hipMemcpyDeviceToHost, s), "stats copy");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  scan_stats& L = g->last;
+  scan_stats L;
   memset(&L, 0, sizeof(L));
   L.edges = g->m;
   const int phase_of_mode[3] = {SCAN_PHASE_CORES, SCAN_PHASE_MERGE, SCAN_PHASE_ATTACH};
@@ -667,6 +667,7 @@ int part_run(scan_graph* g, uint64_t p, uint64_t q, int32_t mu, int32_t* d_label
     (void)hipEventElapsedTime(&ms, g->ev[0], g->ev[SCAN_NUM_PHASES]);
     L.ms_total = ms;
   }
+  set_last(g, L);
   return SCAN_OK;
 }
 
@@ -721,10 +722,11 @@ int part_counts(scan_graph* g, int32_t* h_counts, hipStream_t s) {
   for (auto& x : th) x.join();
   unsigned long long stv[ST_COUNT];
   HIP_TRY(hipMemcpy(stv, g->d_stats, sizeof(stv), hipMemcpyDeviceToHost), "stats copy");
-  g->last = scan_stats();
-  g->last.edges = m;
-  g->last.h2d_bytes = (int64_t)P.h2d_bytes;
-  g->last.group_split = (int64_t)stv[ST_GROUP_SPLIT];
+  scan_stats L{};
+  L.edges = m;
+  L.h2d_bytes = (int64_t)P.h2d_bytes;
+  L.group_split = (int64_t)stv[ST_GROUP_SPLIT];
+  set_last(g, L);
   return SCAN_OK;
 }
 
