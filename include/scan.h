@@ -36,7 +36,8 @@
  * allocated at the first overlap that needs them and kept for later calls
  * until scan_graph_destroy (scan_graph_device_bytes counts them).  A call
  * waits for the graph's own buffers instead when the graph was created with
- * device_budget_bytes and another set would exceed it.  Calls on a
+ * device_budget_bytes and another set would exceed it (the graph's own
+ * output and count staging counted as allocated).  Calls on a
  * partitioned graph and scan_similarity calls on one graph run one at a time.
  * scan_last_stats reports the call that finished last.  Calls on different
  * graphs are independent.

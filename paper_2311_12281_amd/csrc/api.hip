@@ -208,6 +208,14 @@ int scan::collect_stats(scan_graph* g, hipStream_t s, bool timing, const RunStat
 
 uint64_t scan::graph_device_bytes(const scan_graph* g) {
   if (g->partitioned) return 0;
+  const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz;
+  uint64_t b = graph_layout_bytes(g);
+  if (g->d_out_labels) b += 5 * n;
+  if (g->d_counts) b += 4 * nnz;
+  return b + g->extra_bytes.load();
+}
+
+uint64_t scan::graph_layout_bytes(const scan_graph* g) {
   const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, m = (uint64_t)g->m;
   const uint64_t b6 = (uint64_t)(g->bucket_off[kNumBuckets] - g->bucket_off[kNumBuckets - 1]);
   uint64_t b = 8 * (n + 1) + 4 * (nnz + kColPad) + 8 * m + (g->d_edeg ? 8 * m : 0) + sizeof(HubJob) * (uint64_t)g->hub_jobs + 4 * b6 +
@@ -215,9 +223,7 @@ uint64_t scan::graph_device_bytes(const scan_graph* g) {
   if (g->d_hci) b += 4 * (nnz + kColPad);
   if (g->d_hsamp) b += 4 * (uint64_t)sample_lines((int64_t)nnz);
   b += 17 * n + m + 8ull * ST_COUNT + 8ull * kCounters;  // per-run state
-  if (g->d_out_labels) b += 5 * n;
-  if (g->d_counts) b += 4 * nnz;
-  return b + g->extra_bytes.load();
+  return b;
 }
 
 int scan::check_params(const scan_graph* g, int64_t& p, int64_t& q, int32_t mu) {
@@ -304,7 +310,10 @@ ExtraRun* take_extra(scan_graph* g, bool host) {
   const uint64_t want = extra_run_bytes(g, host || (x && x->d_out_labels));
   const uint64_t more = x ? want - std::min(want, x->bytes) : want;
   const uint64_t budget = g->opts.device_budget_bytes;
-  if (budget && more && graph_device_bytes(g) + more > budget) return nullptr;
+  // the graph's own staging (host outputs, counts) is counted as if allocated:
+  // the call holding the graph's buffers may be allocating it right now
+  const uint64_t held = graph_layout_bytes(g) + 5 * (uint64_t)g->n + 4 * (uint64_t)g->nnz + g->extra_bytes.load();
+  if (budget && more && held + more > budget) return nullptr;
   if (!x) {
     g->extra.push_back(std::make_unique<ExtraRun>());
     x = g->extra.back().get();
@@ -644,7 +653,7 @@ int scan_similarity(scan_graph* g, int32_t* counts) {
 
 int scan_last_stats(const scan_graph* g, scan_stats* out) {
   if (!g || !out) return fail(SCAN_E_INVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(const_cast<scan_graph*>(g)->stats_lock);
+  std::lock_guard<std::mutex> lk(g->stats_lock);
   *out = g->last;
   return SCAN_OK;
 }

@@ -132,7 +132,7 @@ struct scan_graph {
   std::mutex pool_lock;  // extra and the sets' busy flags
   std::vector<std::unique_ptr<ExtraRun>> extra;
   std::atomic<uint64_t> extra_bytes{0};
-  std::mutex stats_lock;  // last
+  mutable std::mutex stats_lock;  // last
   scan_stats last{};
 };
 
@@ -184,6 +184,9 @@ int run_counts(scan_graph* g, int32_t* d_counts_arc, int32_t* d_counts_edge, hip
 uint64_t inmemory_footprint(int32_t n, int64_t nnz, bool ranked);
 // Device bytes an in-memory graph holds now (its buffers as allocated).
 uint64_t graph_device_bytes(const scan_graph* g);
+// The part of them fixed at creation (layout and the graph's own per-run
+// state, without the staging allocated on first use).
+uint64_t graph_layout_bytes(const scan_graph* g);
 // Plans blocks and chunks for `budget` device bytes, copies the CSR to pinned
 // memory and allocates the resident state and streaming buffers.
 int part_validate(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, bool full);
