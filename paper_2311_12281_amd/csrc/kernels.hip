@@ -1136,10 +1136,13 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
                 step_hits += (bm[off >> 5] >> (off & 31)) & 1u;
               }
             } else {
-            // first buckets of all elements, then second buckets, in the same registers
+            // first buckets of all elements, then second buckets, in the same
+            // registers; slot compares give per-lane bits, which combine on the
+            // scalar unit
             int4 q[kHubUnroll];
-            uint32_t d[kHubUnroll], b2[kHubUnroll];
+            uint32_t b2[kHubUnroll];
             int32_t w1[kHubUnroll];
+            bool found[kHubUnroll];
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
               uint32_t b1;
@@ -1148,9 +1151,8 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
             }
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              const uint32_t xj = (uint32_t)x[j];
-              d[j] = min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
-                         min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj));
+              const int32_t xj = x[j];
+              found[j] = (q[j].x == xj) | (q[j].y == xj) | (q[j].z == xj) | (q[j].w == xj);
               w1[j] = q[j].w;
             }
 #pragma unroll
@@ -1158,18 +1160,16 @@ void k_hub(EdgeArgs A, const HubJob* jobs, int64_t njobs, unsigned long long* co
             int32_t both_full = -1;  // >= 0 once some element had both buckets full
 #pragma unroll
             for (int j = 0; j < kHubUnroll; ++j) {
-              const uint32_t xj = (uint32_t)x[j];
-              const uint32_t dj = min(d[j], min(min((uint32_t)q[j].x ^ xj, (uint32_t)q[j].y ^ xj),
-                                                min((uint32_t)q[j].z ^ xj, (uint32_t)q[j].w ^ xj)));
-              step_hits += (dj == 0u);
-              d[j] = dj;
+              const int32_t xj = x[j];
+              found[j] = found[j] | (q[j].x == xj) | (q[j].y == xj) | (q[j].z == xj) | (q[j].w == xj);
+              step_hits += found[j] ? 1u : 0u;
               // a bucket is full when its last slot holds an id (>= 0); empty slots hold -1
               both_full = max(both_full, w1[j] | q[j].w);
             }
             if (__ballot(both_full >= 0)) {  // rare: both of some element's buckets full
 #pragma unroll
               for (int j = 0; j < kHubUnroll; ++j)
-                if (d[j] != 0u && (w1[j] | q[j].w) >= 0) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
+                if (!found[j] && (w1[j] | q[j].w) >= 0) step_hits += hub_probe_tail(T4, x[j]) ? 1u : 0u;
             }
             }
             if (exact) {
