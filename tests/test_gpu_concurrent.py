@@ -137,3 +137,56 @@ def test_calls_wait_when_the_budget_has_no_room():
             ol, orr = expect[pm]
             assert_same(lab, rol, ol, orr, f"thread {t} call {k} eps={pm[0]} mu={pm[1]}")
         assert G.device_bytes() == base
+
+
+def test_similarity_and_runs_overlap():
+    """scan_similarity holds the graph's own buffers; scan_run calls started
+    beside it run on buffer sets of the pool, and both are exact."""
+    g = gg.rmat(14, 16, seed=34)
+    oc = oracle.counts(g, threads=oracle.max_threads())
+    expect = _expect(g)
+    with S.Graph.from_csr(g) as G:
+        out = {}
+
+        def work(t):
+            if t == 0:
+                out["counts"] = [G.similarity() for _ in range(3)]
+            else:
+                for k in range(3):
+                    (p, q), mu = pm = PARAMS[(t + k) % len(PARAMS)]
+                    out[(t, k)] = (pm, *G.run(p, q, mu))
+
+        note("rmat14", "scan_similarity beside 3 threads of scan_run")
+        _in_threads(4, work)
+        for c in out.pop("counts"):
+            np.testing.assert_array_equal(c, oc)
+        for (t, k), (pm, lab, rol) in sorted(out.items()):
+            ol, orr = expect[pm]
+            assert_same(lab, rol, ol, orr, f"thread {t} call {k} eps={pm[0]} mu={pm[1]}")
+
+
+def test_partitioned_graph_calls_wait():
+    """A partitioned graph has one set of streaming buffers: overlapping calls
+    wait for each other, hold no pool, and stay exact."""
+    g = gg.rmat(13, 16, seed=35)
+    expect = _expect(g)
+    n, nnz = g.n, g.nnz
+    resident = 8 * (n + 1) + 22 * n + (1 << 20)
+    layout = 8 * (n + 1) + 4 * nnz + 13 * (nnz // 2) + 22 * n + (1 << 20)
+    maxdeg = int(np.diff(g.row_ptr).max())
+    budget = resident + max(int(0.2 * (layout - resident)), 12 * (maxdeg + 64), 1 << 17)
+    with S.Graph.from_csr(g, budget=budget) as G:
+        out = {}
+
+        def work(t):
+            for k in range(2):
+                (p, q), mu = pm = PARAMS[(2 * t + k) % len(PARAMS)]
+                out[(t, k)] = (pm, *G.run(p, q, mu), G.stats()["h2d_bytes"])
+
+        note("rmat13", f"partitioned at budget {budget}: 3 threads x 2 scan_run")
+        _in_threads(3, work)
+        for (t, k), (pm, lab, rol, h2d) in sorted(out.items()):
+            ol, orr = expect[pm]
+            assert_same(lab, rol, ol, orr, f"thread {t} call {k} eps={pm[0]} mu={pm[1]}")
+            assert h2d > 0, "the budget did not select the partition-based path"
+        assert G.device_bytes() == 0
