@@ -190,29 +190,10 @@ def main():
         f"read-only stream {read_bytes >> 20} MiB: {read_ms:.3f} ms -> {read_gbps:.0f} GB/s")
     dom_kernel = "k_hub<0>" if dom == nb - 1 else f"k_group<0, *> (bucket {dom})"
     traffic = _traffic_from_profile(dom_kernel)
-    # every bucket's kernel against the same roofline, and the whole cores pass
-    # byte models of a whole solve: the measured intersections (4 bytes per element consumed + 9 per
-    # intersected edge, every bucket) plus each row read once as the probe side (4 nnz), the offsets
-    # (8 (n + 1)) and the per-vertex state (17 n); beside them, for a solve that evaluates every edge
-    # without pruning, whole smaller lists (4 sum_e min(d_u, d_v) + 9 m) and both lists (the merge
-    # model, 4 sum_e (d_u + d_v) = 4 sum_v d_v^2)
-    deg = np.diff(np.asarray(g.row_ptr)).astype(np.int64)
-    src = np.repeat(np.arange(n, dtype=np.int64), deg)
-    dst = np.asarray(g.col_idx, dtype=np.int64)
-    own = src < dst
-    sum_min = int(np.minimum(deg[src[own]], deg[dst[own]]).sum())
-    sum_both = int((deg * deg).sum())
-    del src, dst, own
-    fixed = 4.0 * g.nnz + 8.0 * (n + 1) + 17.0 * n
-    byte_models = {
-        "per_eps_probe_model_bytes": [
-            float(4.0 * np.sum(s_["cores_bucket_probes"]) + 9.0 * np.sum(s_["cores_bucket_evaluated"]) + fixed)
-            for s_ in stats[-len(EPS_SET):]],
-        "full_evaluation_min_model_bytes": 4.0 * sum_min + 9.0 * m + fixed,
-        "full_evaluation_merge_model_bytes": 4.0 * sum_both,
-        "dominant_kernel_traffic_over_alg": (traffic / float(bytes_b[dom] / launches)) if traffic else None,
-    }
+    byte_models = solve_byte_models(g, stats[-len(EPS_SET):], traffic,
+                                    float(bytes_b[dom] / launches) if launches else None)
     log(f"byte models: {byte_models}")
+    # every bucket's kernel against the same roofline, and the whole cores pass
     # (the intersection bytes above, and beside them the same plus the classification stream:
     # 8 bytes of endpoints, 8 of degrees and 1 of edge state for every edge of the bucket)
     buckets = []
@@ -345,6 +326,33 @@ def main():
     S.scan_device_free(dl10)
     S.scan_device_free(dr10)
     print(json.dumps(line), flush=True)
+
+
+def solve_byte_models(g, stats_per_eps, traffic=None, alg_per_launch=None):
+    """Byte models of a whole solve: the measured intersections (4 bytes per element consumed + 9 per
+    intersected edge, every bucket) plus each row read once as the probe side (4 nnz), the offsets
+    (8 (n + 1)) and the per-vertex state (17 n), one figure per run in stats_per_eps (their
+    cores_bucket_probes and cores_bucket_evaluated); beside them, for a solve that evaluates every edge
+    without pruning, whole smaller lists (4 sum_e min(d_u, d_v) + 9 m) and both lists (the merge model,
+    4 sum_e (d_u + d_v) = 4 sum_v d_v^2); and the dominant kernel's counted traffic over its algorithmic
+    bytes per launch (None without a traffic figure)."""
+    n = int(g.n)
+    deg = np.diff(np.asarray(g.row_ptr)).astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    dst = np.asarray(g.col_idx, dtype=np.int64)
+    own = src < dst
+    m = int(g.m)
+    sum_min = int(np.minimum(deg[src[own]], deg[dst[own]]).sum())
+    sum_both = int((deg * deg).sum())
+    fixed = 4.0 * int(g.nnz) + 8.0 * (n + 1) + 17.0 * n
+    return {
+        "per_eps_probe_model_bytes": [
+            float(4.0 * np.sum(s_["cores_bucket_probes"]) + 9.0 * np.sum(s_["cores_bucket_evaluated"]) + fixed)
+            for s_ in stats_per_eps],
+        "full_evaluation_min_model_bytes": 4.0 * sum_min + 9.0 * m + fixed,
+        "full_evaluation_merge_model_bytes": 4.0 * sum_both,
+        "dominant_kernel_traffic_over_alg": (traffic / alg_per_launch) if traffic and alg_per_launch else None,
+    }
 
 
 def _cpu_model():

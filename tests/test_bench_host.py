@@ -1,9 +1,10 @@
 """Host-side logic of the benchmark script, on the CPU: the one-GPU guard, the
 kernel-time table of a rocprofv3 --kernel-trace --stats run, the counter
 summary (FETCH_SIZE and WRITE_SIZE scaled by what they read for the plain copy
-kernel, per-bucket traffic, LDS ratios), and the rule that the committed
-traffic figure is used only while the kernel sources are the ones it was
-measured on.  The CSV fixtures use rocprofv3's column names and kernel-name
+kernel, per-bucket traffic, LDS ratios), the rule that the committed traffic
+figure is used only while the kernel sources are the ones it was measured on,
+and the byte models of a solve on a graph small enough to count by hand.  The
+CSV fixtures use rocprofv3's column names and kernel-name
 strings, with made-up values chosen so that every expected figure is exact."""
 import argparse
 import os
@@ -152,3 +153,19 @@ def test_traffic_figure_follows_the_sources(tmp_path, monkeypatch, capsys):
     assert bench._traffic_from_profile("k_hub<0>") is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench._traffic_from_profile("k_hub<0>") is None
+
+
+def test_solve_byte_models():
+    import graphgen as gg
+    # a triangle 0-1-2 with a pendant 3 on vertex 2: degrees 2, 2, 3, 1
+    g = gg.from_edges(4, [(0, 1), (1, 2), (2, 0), (2, 3)])
+    fixed = 4 * 8 + 8 * 5 + 17 * 4  # rows, offsets, per-vertex state
+    stats = [{"cores_bucket_probes": [1, 2, 0, 0, 0, 0, 3], "cores_bucket_evaluated": [1, 0, 0, 0, 0, 0, 1]},
+             {"cores_bucket_probes": [0] * 7, "cores_bucket_evaluated": [0] * 7}]
+    bm = bench.solve_byte_models(g, stats, traffic=300.0, alg_per_launch=150.0)
+    assert bm["per_eps_probe_model_bytes"] == [4 * 6 + 9 * 2 + fixed, fixed]
+    # smaller sides 2, 2, 2, 1 over the four edges; squares of the degrees 4 + 4 + 9 + 1
+    assert bm["full_evaluation_min_model_bytes"] == 4 * 7 + 9 * 4 + fixed
+    assert bm["full_evaluation_merge_model_bytes"] == 4 * 18
+    assert bm["dominant_kernel_traffic_over_alg"] == 2.0
+    assert bench.solve_byte_models(g, [], traffic=None, alg_per_launch=150.0)["dominant_kernel_traffic_over_alg"] is None
